@@ -1,0 +1,24 @@
+"""CPU FP64 oracle for the planar photoacoustic Fourier reconstruction.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call, link
+or execute anything in this package: only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the
+HIP library: node positions, weights, transforms and scaling are written out
+here from the paper's definitions, independently of ``paper_0808_3510_amd``.
+
+Modules
+-------
+``recon``  direct Fourier reconstruction R (Section 4, eqs. fft-1a, fft-2,
+           fft-0, fft-1; "direct Fourier algorithm" of Section 4), its
+           transpose, the spectral forward model A and its transpose, all by
+           direct nonuniform DFT sums.
+``kb``     the Kaiser-Bessel window and its Fourier transform (Section 3.2).
+``nufft``  the paper's NUFFT (Section 3.1, Proposition on the NUFFT identity
+           and the NUFFT algorithm), used only to pin the readings of its
+           constant and phase against the direct sum.
+
+Parity status: every function is pinned by a test under ``tests/`` against a
+closed form, a printed value of the paper, a library routine on a special case
+or a transpose identity; none is "parity unpinned".
+"""
+from . import kb, nufft, recon  # noqa: F401
