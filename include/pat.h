@@ -1,0 +1,163 @@
+/*
+ * pat.h - C ABI of libpatnufft: NUFFT-based Fourier reconstruction for
+ * photoacoustic imaging with a planar (3D) or line (2D) detector array.
+ *
+ * The operation is the partial Fourier reconstruction f^dagger of the paper's
+ * Section 2 (eq. inv2), discretised as in Section 4 (eqs. gd, fd, dft-2d,
+ * fft-1a, fft-2, fft-0, fft-1) and evaluated with the one-dimensional
+ * nonuniform FFT of Section 3 (Proposition on the NUFFT identity, eqs.
+ * nufft-a / nufft-c, the NUFFT algorithm, Kaiser-Bessel window of Section
+ * 3.2): detector data p(x, t) in, initial pressure f(x, z) out.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are C-contiguous.  Detector data p has shape (nx[0], nx[1], nt)
+ *    with time fastest; images f have shape (nx[0], nx[1], nz) with depth
+ *    fastest.  The 2D line-detector geometry uses ndim = 2 and nx[1] = 1.
+ *  - Detector m sits at x = m*dx on the plane y = 0, sample n at t = n*dt,
+ *    image sample q at depth y = q*dz (Section 4 discretisation).
+ *  - Element type: double for PAT_F64, float for PAT_F32 and
+ *    PAT_F32_BF16GRID (the latter stores only the oversampled grid in bf16).
+ *  - Every device pointer is caller-owned device memory on the device that is
+ *    current when the call is made, 16-byte aligned.  The library allocates
+ *    no device memory: the plan's constant tables live in a caller buffer of
+ *    pat_plan_sizes().table_bytes filled by pat_plan_upload(), and every
+ *    transform takes a caller workspace of pat_plan_sizes().workspace_bytes.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work; results are ready when the stream is.
+ *  - Errors: every argument is validated before anything is enqueued, so a
+ *    non-OK status means nothing was written.  A HIP launch failure reports
+ *    PAT_ERR_HIP; an asynchronous fault of earlier work surfaces on a later
+ *    HIP call.  pat_last_error() gives a thread-local message for the last
+ *    non-OK status.  No C++ exception crosses this boundary.
+ *  - A plan may be used from one host thread at a time; different plans are
+ *    independent.  Calls that share a workspace must be stream-ordered.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAT_OK = 0,
+  PAT_ERR_INVALID_ARG = 1, /* null/misaligned pointer, bad geometry value */
+  PAT_ERR_UNSUPPORTED = 2, /* valid but outside what this build supports */
+  PAT_ERR_WORKSPACE = 3,   /* table not uploaded / workspace missing */
+  PAT_ERR_HIP = 4,         /* a HIP runtime call failed */
+  PAT_ERR_INTERNAL = 5
+} pat_status;
+
+typedef enum {
+  PAT_F64 = 0,          /* every stage in double */
+  PAT_F32 = 1,          /* float; node, phase, weight and deconvolution
+                           factors formed in double */
+  PAT_F32_BF16GRID = 2  /* as PAT_F32, oversampled grid stored as bf16 */
+} pat_precision;
+
+/*
+ * Geometry and NUFFT parameters.
+ *  ndim      2 (line detectors, nx[1] must be 1) or 3 (planar array).
+ *  nx[0..1]  detectors per transverse axis; even (nx[1] = 1 allowed in 2D),
+ *            2 <= nx <= 4096.
+ *  nt, nz    time samples and output depth samples; even, 2 <= . <= 8192.
+ *  dx,dt,dz  detector spacing, time step, depth spacing (> 0).
+ *  vs        speed of sound (> 0).
+ *  c         oversampling factor of the NUFFT (Section 3.1, eq. nufft-c),
+ *            c > 1 with c*nt an even integer.
+ *  K         interpolation length (Section 3.1 step (ii)); 2*c*K must be an
+ *            integer between 2 and 64 (the number of taps per node).
+ *  alpha     Kaiser-Bessel width (Section 3.2), pi < alpha < pi*(2c-1);
+ *            0 selects 0.98*pi*(2c-1) ("slightly smaller than pi(2c-1)",
+ *            Section 5).
+ *  precision a pat_precision.
+ * Every FFT length (nx[0], nx[1], nz, c*nt) must factor into primes <= 23.
+ */
+typedef struct {
+  int32_t ndim;
+  int32_t nx[2];
+  int32_t nt, nz;
+  double dx, dt, dz, vs;
+  double c, K, alpha;
+  int32_t precision;
+} pat_geometry;
+
+typedef struct pat_plan pat_plan;
+
+/* Host-only: validates the geometry and builds the FP64 constant tables
+ * (deconvolution factors 1/Psi(2 pi n/nt - pi), FFT twiddles, index maps).
+ * Never touches the GPU.  *out receives a new plan, freed by
+ * pat_plan_destroy(). */
+pat_status pat_plan_create(const pat_geometry* geom, pat_plan** out);
+
+/* Bytes of the device table buffer and of the workspace every transform of
+ * this plan needs.  Either output pointer may be NULL. */
+pat_status pat_plan_sizes(const pat_plan* plan, size_t* table_bytes, size_t* workspace_bytes);
+
+/* Copies the plan's tables into table_dev (table_bytes, caller-owned, must
+ * stay alive while the plan is used) on `stream`, then synchronises the
+ * stream.  Must precede any transform. */
+pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream);
+
+/* R: reconstruction (Section 4, the NUFFT-based algorithm).  p -> f.
+ *   a1  DFT over the detector axes (eq. fft-1a),
+ *   a2  deconvolution by 1/Psi, zero padding to c*nt, FFT (eq. nufft-c),
+ *   a3  2cK-tap Kaiser-Bessel interpolation at the nodes
+ *       nu_{k,l} = sign(l) nt dt vs |K| / (2 pi) (eqs. nufft-a, dft-2d),
+ *       times the Jacobian weight 2 vs (dt/dz) |K_z| / |K| (eqs. fft-0, inv),
+ *   a4, a5  inverse DFT over depth and detector axes, real part (eq. fft-1).
+ * The weight is 0 on the plane l = 0; on the depth-Nyquist plane l = -nz/2
+ * the value is the mean of the two nodes +-|nu| (the real part of eq. fft-1).
+ * p, f: device arrays as described above.  ws: workspace_bytes. */
+pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, void* stream);
+
+/* R^T: the exact transpose of R for the real inner product (type-1 NUFFT
+ * spreading; the gradient of R).  f-shaped input -> p-shaped output. */
+pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, void* p, void* ws, void* stream);
+
+/* A: the spectral forward model of the wave problem of Section 2 on the
+ * periodic sampling grid, p[m, n] = Re( IDFT_x( (1/nz) sum_l F[k, l]
+ * cos(2 pi |nu_{k,l}| n / nt) ) ), F the DFT of f over all axes; evaluated as
+ * a type-1 NUFFT (spreading to the nodes +-|nu|).  f -> p. */
+pat_status pat_forward(pat_plan* plan, const void* f, void* p, void* ws, void* stream);
+
+/* A^T: transpose of A (type-2 interpolation at +-|nu|).  p -> f-shaped. */
+pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws, void* stream);
+
+/* R for n independent plans (1 <= n <= 32) in one launch per stage: work
+ * items (instance, tile or line) are drawn from a device work counter by a
+ * persistent grid.  All plans must share one precision.  p[i], f[i] as for
+ * pat_reconstruct of plans[i]; ws of pat_batched_workspace_size() bytes. */
+pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes);
+pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p,
+                                   void* const* f, void* ws, void* stream);
+
+/* Stage a3 alone (type-2 interpolation + weight) on the half spectrum:
+ * grid: ((nx[0]/2+1)*nx[1], c*nt) complex oversampled line spectra in the
+ * plan's grid storage (interleaved re,im; float, double or bf16 pairs),
+ * as produced by a2 (line (k1, k2) at row k1*nx[1] + k2, k2 in DFT order);
+ * out: ((nx[0]/2+1)*nx[1], nz) complex in the plan's element type, l in DFT
+ * order, already scaled by 1/(nx[0] nx[1] nz). */
+pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream);
+
+/* Per-stage timing of the plan's last transform.  pat_plan_set_timing(plan,1)
+ * makes later transforms record a hipEvent before and after every kernel on
+ * their stream; pat_plan_stage_times() then synchronises on the last event
+ * and writes up to `cap` entries: names[i] (static strings) and ms[i].
+ * Returns the number of stages through *count. */
+pat_status pat_plan_set_timing(pat_plan* plan, int32_t on);
+pat_status pat_plan_stage_times(pat_plan* plan, int32_t cap, const char** names, float* ms,
+                                int32_t* count);
+
+void pat_plan_destroy(pat_plan* plan);
+const char* pat_status_string(pat_status s);
+const char* pat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAT_H */

@@ -1,0 +1,250 @@
+// C ABI of libpatnufft (declared in include/pat.h).  Validates every argument
+// before enqueueing anything and converts failures into status codes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pat_status set_err(pat_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+pat_status hip_err(hipError_t e, const char* where) {
+  return set_err(PAT_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// hipEvent pairs around each kernel of a transform.
+class EventTimer : public pat::StageTimer {
+ public:
+  ~EventTimer() override {
+    for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
+  }
+  void reset() {
+    names_.clear();
+    used_ = 0;
+  }
+  void begin(const char* name, hipStream_t s) override {
+    names_.push_back(name);
+    (void)hipEventRecord(get(), s);
+  }
+  void end(hipStream_t s) override { (void)hipEventRecord(get(), s); }
+  int count() const { return (int)names_.size(); }
+  const char* name(int i) const { return names_[i]; }
+  float ms(int i) {
+    float v = 0.f;
+    (void)hipEventSynchronize(ev_[2 * i + 1]);
+    (void)hipEventElapsedTime(&v, ev_[2 * i], ev_[2 * i + 1]);
+    return v;
+  }
+
+ private:
+  hipEvent_t get() {
+    if (used_ == ev_.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      ev_.push_back(e);
+    }
+    return ev_[used_++];
+  }
+  std::vector<const char*> names_;
+  std::vector<hipEvent_t> ev_;
+  size_t used_ = 0;
+};
+
+EventTimer* timer_of(pat_plan* p) {
+  if (!p->timing) return nullptr;
+  if (!p->timer) p->timer = new (std::nothrow) EventTimer();
+  EventTimer* t = static_cast<EventTimer*>(p->timer);
+  if (t) t->reset();
+  return t;
+}
+
+pat_status check_plan(const pat_plan* p) {
+  if (!p) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->uploaded) return set_err(PAT_ERR_WORKSPACE, "plan tables not uploaded (pat_plan_upload)");
+  return PAT_OK;
+}
+
+pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, void* stream) {
+  pat_status s = check_plan(plan);
+  if (s != PAT_OK) return s;
+  if (!aligned16(in) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
+  if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
+  const pat::Inst* dd[1] = {d};
+  const void* ins[1] = {in};
+  void* outs[1] = {out};
+  void* wss[1] = {ws};
+  hipError_t e = pat::run_op(plan->prec, op, 1, &plan->inst, dd, ins, outs, wss, nullptr,
+                             static_cast<hipStream_t>(stream), timer_of(plan));
+  if (e != hipSuccess) return hip_err(e, "kernel launch");
+  return PAT_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+pat_status pat_plan_create(const pat_geometry* geom, pat_plan** out) {
+  if (!geom || !out) return set_err(PAT_ERR_INVALID_ARG, "geometry or output pointer is NULL");
+  *out = nullptr;
+  pat_plan* p = new (std::nothrow) pat_plan();
+  if (!p) return set_err(PAT_ERR_INTERNAL, "out of host memory");
+  std::string err;
+  pat_status s;
+  try {
+    s = pat::build_plan(*geom, p, &err);
+  } catch (...) {
+    s = PAT_ERR_INTERNAL;
+    err = "exception while building the plan";
+  }
+  if (s != PAT_OK) {
+    delete p;
+    return set_err(s, err);
+  }
+  *out = p;
+  return PAT_OK;
+}
+
+pat_status pat_plan_sizes(const pat_plan* plan, size_t* table_bytes, size_t* workspace_bytes) {
+  if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
+  if (table_bytes) *table_bytes = plan->table_bytes;
+  if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
+  return PAT_OK;
+}
+
+pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream) {
+  if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
+  if (!aligned16(table_dev)) return set_err(PAT_ERR_INVALID_ARG, "table buffer NULL or not 16-byte aligned");
+  pat::bind_table(plan, table_dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(table_dev, plan->blob.data(), plan->table_bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(e, "hipMemcpyAsync(table)");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+  plan->uploaded = true;
+  return PAT_OK;
+}
+
+pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, void* stream) {
+  return run(plan, pat::OP_R, p, f, ws, stream);
+}
+
+pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, void* p, void* ws, void* stream) {
+  return run(plan, pat::OP_RT, f, p, ws, stream);
+}
+
+pat_status pat_forward(pat_plan* plan, const void* f, void* p, void* ws, void* stream) {
+  return run(plan, pat::OP_A, f, p, ws, stream);
+}
+
+pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws, void* stream) {
+  return run(plan, pat::OP_AT, p, f, ws, stream);
+}
+
+pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes) {
+  if (!plans || !workspace_bytes) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > pat::kMaxBatch) return set_err(PAT_ERR_INVALID_ARG, "batch size must be in [1, 32]");
+  size_t total = align256(pat::kNumCounters * sizeof(uint32_t));
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return set_err(PAT_ERR_INVALID_ARG, "NULL plan in batch");
+    total += align256(plans[i]->ws_bytes);
+  }
+  *workspace_bytes = total;
+  return PAT_OK;
+}
+
+pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p, void* const* f, void* ws,
+                                   void* stream) {
+  if (!plans || !p || !f) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > pat::kMaxBatch) return set_err(PAT_ERR_INVALID_ARG, "batch size must be in [1, 32]");
+  if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  pat::Inst h[pat::kMaxBatch];
+  const pat::Inst* d[pat::kMaxBatch];
+  void* wsi[pat::kMaxBatch];
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(w);
+  size_t off = align256(pat::kNumCounters * sizeof(uint32_t));
+  for (int i = 0; i < n; ++i) {
+    pat_status s = check_plan(plans[i]);
+    if (s != PAT_OK) return s;
+    if (plans[i]->prec != plans[0]->prec) return set_err(PAT_ERR_INVALID_ARG, "plans in a batch must share a precision");
+    if (!aligned16(p[i]) || !aligned16(f[i]))
+      return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
+    h[i] = plans[i]->inst;
+    d[i] = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plans[i]->table_dev) + plans[i]->off_desc);
+    wsi[i] = w + off;
+    off += align256(plans[i]->ws_bytes);
+  }
+  hipError_t e = pat::run_op(plans[0]->prec, pat::OP_R, n, h, d, p, f, wsi, counters,
+                             static_cast<hipStream_t>(stream), timer_of(plans[0]));
+  if (e != hipSuccess) return hip_err(e, "kernel launch");
+  return PAT_OK;
+}
+
+pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream) {
+  pat_status s = check_plan(plan);
+  if (s != PAT_OK) return s;
+  if (!aligned16(grid) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "grid/out NULL or not 16-byte aligned");
+  const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
+  hipError_t e = pat::run_interp(plan->prec, plan->inst, d, grid, out, static_cast<hipStream_t>(stream), timer_of(plan));
+  if (e != hipSuccess) return hip_err(e, "kernel launch");
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_timing(pat_plan* plan, int32_t on) {
+  if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
+  plan->timing = on != 0;
+  return PAT_OK;
+}
+
+pat_status pat_plan_stage_times(pat_plan* plan, int32_t cap, const char** names, float* ms, int32_t* count) {
+  if (!plan || !count) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
+  *count = 0;
+  EventTimer* t = static_cast<EventTimer*>(plan->timer);
+  if (!t) return PAT_OK;
+  const int n = t->count();
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (names) names[i] = t->name(i);
+    if (ms) ms[i] = t->ms(i);
+  }
+  *count = n;
+  return PAT_OK;
+}
+
+void pat_plan_destroy(pat_plan* plan) {
+  if (!plan) return;
+  delete static_cast<EventTimer*>(plan->timer);
+  delete plan;
+}
+
+const char* pat_status_string(pat_status s) {
+  switch (s) {
+    case PAT_OK: return "PAT_OK";
+    case PAT_ERR_INVALID_ARG: return "PAT_ERR_INVALID_ARG";
+    case PAT_ERR_UNSUPPORTED: return "PAT_ERR_UNSUPPORTED";
+    case PAT_ERR_WORKSPACE: return "PAT_ERR_WORKSPACE";
+    case PAT_ERR_HIP: return "PAT_ERR_HIP";
+    case PAT_ERR_INTERNAL: return "PAT_ERR_INTERNAL";
+  }
+  return "PAT_ERR_UNKNOWN";
+}
+
+const char* pat_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// Host-side entry points of the kernel layer (kernels.hip), used by capi.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pat_internal.h"
+
+namespace pat {
+
+enum Op { OP_R = 0, OP_RT = 1, OP_A = 2, OP_AT = 3 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+// Records a pair of events around every kernel launch when attached.
+struct StageTimer {
+  virtual void begin(const char* name, hipStream_t s) = 0;
+  virtual void end(hipStream_t s) = 0;
+  virtual ~StageTimer() {}
+};
+
+// One operator over n instances.  hinst: host copies of the descriptors,
+// dinst: their device addresses.  in/out: user arrays; ws: per-instance
+// workspace bases.  counters: kNumCounters zeroed words of device memory for
+// the persistent work queue, or nullptr for one workgroup per work item.
+hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst,
+                  const void* const* in, void* const* out, void* const* ws, uint32_t* counters,
+                  hipStream_t stream, StageTimer* timer);
+
+// Stage a3 alone on user buffers (grid in, weighted node values out).
+hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* grid, void* out,
+                      hipStream_t stream, StageTimer* timer);
+
+}  // namespace pat

@@ -1,0 +1,57 @@
+// Internal data shared by the host plan (plan.cpp), the kernels
+// (kernels.hip) and the C ABI layer (capi.cpp).  Plain structs only: the
+// descriptor is built on the host in FP64 and copied verbatim to the device.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pat {
+
+constexpr int kMaxStages = 16;   // radix stages of one FFT
+constexpr int kMaxBatch = 32;    // instances in one batched call
+constexpr int kMaxTaps = 64;     // 2cK
+constexpr int kBlock = 256;      // threads per workgroup of every kernel
+constexpr int kNumCounters = 16; // persistent work counters per batched call
+
+// One FFT length: in-place decimation-in-frequency mixed-radix factorisation.
+// After the transform the natural-order bin k sits at LDS position perm[k].
+struct FftDesc {
+  int32_t L;
+  int32_t nst;
+  int32_t rad[kMaxStages];
+  int32_t tw;    // element offset of the L roots exp(-2 pi i k / L) in the twiddle table
+  int32_t perm;  // element offset of the bin -> position map in the index table
+};
+
+// Everything a kernel needs about one reconstruction instance.
+struct Inst {
+  int32_t n1, n2, nt, nz, m;  // detectors, time samples, depth samples, c*nt
+  int32_t h1;                 // n1/2 + 1 (half spectrum over the first axis)
+  int32_t lines;              // h1 * n2 frequency lines
+  int32_t taps;               // 2cK
+  int32_t tb;                 // batch width of the transverse tiles
+  int32_t pad_;
+  double c, K, alpha;
+  double ck;                  // c*K
+  // node and weight:  nu+^2 = a1 k1^2 + a2 k2^2 + b l^2 ;  W = wcoef |l| / nu+
+  double a1, a2, b, wcoef;
+  // 1 / (pi c n1 n2 nz): the 1/(2 pi c) of the NUFFT identity with the factor
+  // 2 e^{alpha K} folded into the deconvolution table, and the inverse-DFT
+  // normalisation.
+  double scale;
+  FftDesc f1, f2, fm, fz;
+  // device addresses inside this instance's table buffer (set at upload)
+  const void* tw;        // cplx<T>[]
+  const int32_t* perm;   // int32[]
+  const void* sn;        // T[nt]: e^{alpha K} / I0(K sqrt(alpha^2 - theta_n^2))
+  // workspace byte offsets
+  int64_t off_g, off_u, off_f;
+};
+
+// Host-side plan (see pat.h).
+struct HostTables {
+  size_t desc_off, tw_off, perm_off, sn_off, total;
+};
+
+}  // namespace pat

@@ -1,0 +1,321 @@
+// Host-side plan: geometry validation and the FP64 constant tables
+// (deconvolution factors, FFT twiddles and index maps, node/weight constants).
+#include "plan.h"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+namespace pat {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Radices for an in-place DIF transform of length L: eights for the powers of
+// two (a 2 or 4 absorbed as 4 or 4*4), then the odd primes.  Empty for L = 1.
+bool factorize(int L, std::vector<int>* rad) {
+  rad->clear();
+  int e = 0;
+  while (L % 2 == 0) {
+    L /= 2;
+    ++e;
+  }
+  int n8 = e / 3;
+  const int rem = e % 3;
+  std::vector<int> small;
+  if (rem == 1) {
+    if (n8 > 0) {
+      --n8;
+      small = {4, 4};
+    } else {
+      small = {2};
+    }
+  } else if (rem == 2) {
+    small = {4};
+  }
+  for (int i = 0; i < n8; ++i) rad->push_back(8);
+  for (int r : small) rad->push_back(r);
+  static const int odd[] = {3, 5, 7, 11, 13, 17, 19, 23};
+  for (int p : odd) {
+    while (L % p == 0) {
+      L /= p;
+      rad->push_back(p);
+    }
+  }
+  return L == 1 && (int)rad->size() <= kMaxStages;
+}
+
+// Position of natural-order bin k after the in-place DIF transform:
+// k = d1 + R1 (d2 + R2 (...)),  pos = sum_i d_i L / (R1 ... Ri).
+std::vector<int32_t> dif_positions(int L, const std::vector<int>& rad) {
+  std::vector<int32_t> pos(L);
+  for (int k = 0; k < L; ++k) {
+    int rest = k, span = L, p = 0;
+    for (int r : rad) {
+      span /= r;
+      p += (rest % r) * span;
+      rest /= r;
+    }
+    pos[k] = p;
+  }
+  return pos;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bool is_int(double v, double tol = 1e-9) { return std::fabs(v - std::nearbyint(v)) <= tol * std::fmax(1.0, std::fabs(v)); }
+
+template <typename T>
+void put(std::vector<unsigned char>& blob, size_t off, const T* v, size_t n) {
+  std::memcpy(blob.data() + off, v, n * sizeof(T));
+}
+
+}  // namespace
+
+double bessel_i0e(double z) {
+  // sum_k (z^2/4)^k / (k!)^2, each term carried with the factor e^{-z} so that
+  // nothing overflows for z up to ~700.
+  const double q = 0.25 * z * z;
+  double term = std::exp(-z);
+  double sum = term;
+  for (int k = 1; k < 100000; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum && k > z) break;
+  }
+  return sum;
+}
+
+size_t complex_bytes(int prec) { return prec == PAT_F64 ? 16 : 8; }
+size_t grid_bytes(int prec) { return prec == PAT_F64 ? 16 : (prec == PAT_F32 ? 8 : 4); }
+
+pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
+  std::ostringstream msg;
+  auto fail = [&](pat_status s) {
+    *err = msg.str();
+    return s;
+  };
+  pat_geometry g = gin;
+  if (g.ndim != 2 && g.ndim != 3) {
+    msg << "ndim must be 2 or 3 (got " << g.ndim << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  if (g.ndim == 2 && g.nx[1] != 1) {
+    msg << "ndim = 2 needs nx[1] = 1 (got " << g.nx[1] << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  for (int a = 0; a < g.ndim - 1; ++a) {
+    if (g.nx[a] < 2 || g.nx[a] % 2 != 0) {
+      msg << "nx[" << a << "] must be even and >= 2 (got " << g.nx[a] << ")";
+      return fail(PAT_ERR_INVALID_ARG);
+    }
+    if (g.nx[a] > 4096) {
+      msg << "nx[" << a << "] = " << g.nx[a] << " exceeds 4096";
+      return fail(PAT_ERR_UNSUPPORTED);
+    }
+  }
+  if (g.nt < 2 || g.nt % 2 != 0 || g.nz < 2 || g.nz % 2 != 0) {
+    msg << "nt and nz must be even and >= 2 (got " << g.nt << ", " << g.nz << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  if (g.nt > 8192 || g.nz > 8192) {
+    msg << "nt, nz above 8192 are not supported";
+    return fail(PAT_ERR_UNSUPPORTED);
+  }
+  if (!finite_pos(g.dx) || !finite_pos(g.dt) || !finite_pos(g.dz) || !finite_pos(g.vs)) {
+    msg << "dx, dt, dz, vs must be finite and > 0";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  if (g.precision < PAT_F64 || g.precision > PAT_F32_BF16GRID) {
+    msg << "unknown precision " << g.precision;
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  if (!std::isfinite(g.c) || g.c <= 1.0) {
+    msg << "oversampling c must be > 1 (got " << g.c << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  const double mreal = g.c * g.nt;
+  if (!is_int(mreal) || ((long long)std::nearbyint(mreal)) % 2 != 0) {
+    msg << "c*nt must be an even integer (got " << mreal << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  const int m = (int)std::nearbyint(mreal);
+  if (!std::isfinite(g.K) || g.K <= 0.0) {
+    msg << "K must be > 0";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  const double tr = 2.0 * g.c * g.K;
+  if (!is_int(tr) || std::nearbyint(tr) < 2 || std::nearbyint(tr) > kMaxTaps) {
+    msg << "2cK must be an integer in [2, " << kMaxTaps << "] (got " << tr << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  const int taps = (int)std::nearbyint(tr);
+  if (m < taps) {
+    msg << "c*nt = " << m << " is smaller than the " << taps << " taps";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  const double amax = kPi * (2.0 * g.c - 1.0);
+  if (g.alpha == 0.0) g.alpha = 0.98 * amax;
+  if (!std::isfinite(g.alpha) || !(g.alpha > kPi) || !(g.alpha < amax)) {
+    msg << "alpha must satisfy pi < alpha < pi(2c-1) = " << amax << " (got " << g.alpha << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  if (g.alpha * g.K > 700.0) {
+    msg << "alpha*K = " << g.alpha * g.K << " exceeds 700";
+    return fail(PAT_ERR_UNSUPPORTED);
+  }
+  const int prec = g.precision;
+  const size_t cs = complex_bytes(prec);
+  const size_t rs = cs / 2;
+  if ((size_t)m * cs > 131072) {
+    msg << "c*nt = " << m << " exceeds the LDS line capacity for this precision";
+    return fail(PAT_ERR_UNSUPPORTED);
+  }
+
+  const int n1 = g.nx[0];
+  const int n2 = g.ndim == 3 ? g.nx[1] : 1;
+  // FFT plans for every distinct length
+  const int lens[4] = {n1, n2, m, g.nz};
+  std::vector<int> uniq;
+  for (int L : lens) {
+    bool seen = false;
+    for (int u : uniq) seen = seen || (u == L);
+    if (!seen) uniq.push_back(L);
+  }
+  std::vector<std::vector<int>> rads(uniq.size());
+  for (size_t i = 0; i < uniq.size(); ++i) {
+    if (!factorize(uniq[i], &rads[i])) {
+      msg << "FFT length " << uniq[i] << " has a prime factor above 23";
+      return fail(PAT_ERR_UNSUPPORTED);
+    }
+  }
+
+  Inst I;
+  std::memset(&I, 0, sizeof(I));
+  I.n1 = n1;
+  I.n2 = n2;
+  I.nt = g.nt;
+  I.nz = g.nz;
+  I.m = m;
+  I.h1 = n1 / 2 + 1;
+  I.lines = I.h1 * n2;
+  I.taps = taps;
+  int tb = 32;
+  const int lmax = n1 > n2 ? n1 : n2;
+  while (tb > 1 && (size_t)lmax * tb * cs > 65536) tb /= 2;
+  I.tb = tb;
+  I.c = g.c;
+  I.K = g.K;
+  I.alpha = g.alpha;
+  I.ck = g.c * g.K;
+  const double tv = g.nt * g.dt * g.vs;
+  I.a1 = (tv / (n1 * g.dx)) * (tv / (n1 * g.dx));
+  I.a2 = g.ndim == 3 ? (tv / (n2 * g.dx)) * (tv / (n2 * g.dx)) : 0.0;
+  I.b = (tv / (g.nz * g.dz)) * (tv / (g.nz * g.dz));
+  I.wcoef = 2.0 * g.vs * (g.dt / g.dz) * std::sqrt(I.b);
+  I.scale = 1.0 / (kPi * g.c * (double)n1 * (double)n2 * (double)g.nz);
+
+  // table layout
+  size_t off = align256(sizeof(Inst));
+  const size_t off_tw = off;
+  std::vector<size_t> tw_at(uniq.size());
+  size_t tw_elems = 0;
+  for (size_t i = 0; i < uniq.size(); ++i) {
+    tw_at[i] = tw_elems;
+    tw_elems += uniq[i];
+  }
+  off = align256(off + tw_elems * cs);
+  const size_t off_perm = off;
+  std::vector<size_t> perm_at(uniq.size());
+  size_t perm_elems = 0;
+  for (size_t i = 0; i < uniq.size(); ++i) {
+    perm_at[i] = perm_elems;
+    perm_elems += uniq[i];
+  }
+  off = align256(off + perm_elems * sizeof(int32_t));
+  const size_t off_sn = off;
+  off = align256(off + (size_t)g.nt * rs);
+  const size_t total = off;
+
+  p->blob.assign(total, 0);
+  for (size_t i = 0; i < uniq.size(); ++i) {
+    const int L = uniq[i];
+    for (int k = 0; k < L; ++k) {
+      // exp(-2 pi i k / L), argument formed from the reduced fraction k/L
+      const double ang = 2.0 * kPi * ((double)k / (double)L);
+      const double re = std::cos(ang), im = -std::sin(ang);
+      const size_t o = off_tw + (tw_at[i] + k) * cs;
+      if (prec == PAT_F64) {
+        const double v[2] = {re, im};
+        put(p->blob, o, v, 2);
+      } else {
+        const float v[2] = {(float)re, (float)im};
+        put(p->blob, o, v, 2);
+      }
+    }
+    const std::vector<int32_t> pos = dif_positions(L, rads[i]);
+    put(p->blob, off_perm + perm_at[i] * sizeof(int32_t), pos.data(), pos.size());
+  }
+  auto desc_of = [&](int L) {
+    FftDesc d;
+    std::memset(&d, 0, sizeof(d));
+    for (size_t i = 0; i < uniq.size(); ++i) {
+      if (uniq[i] == L) {
+        d.L = L;
+        d.nst = (int)rads[i].size();
+        for (size_t s = 0; s < rads[i].size(); ++s) d.rad[s] = rads[i][s];
+        d.tw = (int32_t)tw_at[i];
+        d.perm = (int32_t)perm_at[i];
+      }
+    }
+    return d;
+  };
+  I.f1 = desc_of(n1);
+  I.f2 = desc_of(n2);
+  I.fm = desc_of(m);
+  I.fz = desc_of(g.nz);
+  // deconvolution factors e^{alpha K} / I0(K sqrt(alpha^2 - theta_n^2)),
+  // theta_n = 2 pi n / nt - pi  (eq. nufft-c with Psi the Kaiser-Bessel window)
+  for (int n = 0; n < g.nt; ++n) {
+    const double th = 2.0 * kPi * ((double)n / (double)g.nt) - kPi;
+    const double z = g.K * std::sqrt(g.alpha * g.alpha - th * th);
+    const double s = std::exp(g.alpha * g.K - z) / bessel_i0e(z);
+    const size_t o = off_sn + (size_t)n * rs;
+    if (prec == PAT_F64) {
+      put(p->blob, o, &s, 1);
+    } else {
+      const float f = (float)s;
+      put(p->blob, o, &f, 1);
+    }
+  }
+  // workspace: G (lines x nt), grid (lines x m), F (lines x nz)
+  const size_t lines = (size_t)I.lines;
+  I.off_g = 0;
+  I.off_u = (int64_t)align256(lines * g.nt * cs);
+  I.off_f = I.off_u + (int64_t)align256(lines * (size_t)m * grid_bytes(prec));
+  p->ws_bytes = (size_t)I.off_f + align256(lines * g.nz * cs);
+
+  p->g = g;
+  p->prec = prec;
+  p->inst = I;
+  p->off_desc = 0;
+  p->off_tw = off_tw;
+  p->off_perm = off_perm;
+  p->off_sn = off_sn;
+  p->table_bytes = total;
+  return PAT_OK;
+}
+
+void bind_table(pat_plan* p, void* table_dev) {
+  unsigned char* base = static_cast<unsigned char*>(table_dev);
+  p->inst.tw = base + p->off_tw;
+  p->inst.perm = reinterpret_cast<const int32_t*>(base + p->off_perm);
+  p->inst.sn = base + p->off_sn;
+  std::memcpy(p->blob.data() + p->off_desc, &p->inst, sizeof(Inst));
+  p->table_dev = table_dev;
+}
+
+}  // namespace pat

@@ -1,0 +1,320 @@
+"""Python binding of ``libpatnufft.so`` (the C ABI in ``include/pat.h``).
+
+Argument marshalling only: every stage of every operator runs in the HIP
+library.  The functions ``pat_*`` mirror the C entry points one to one; the
+:class:`Plan` class bundles a plan with its device table and workspace (torch
+tensors on the caller's device) and checks dtype, device, contiguity and
+shape before calling in.  There is no CPU fallback: without the built library
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, byref, c_char_p, c_double, c_float, c_int32, c_size_t, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpatnufft.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pat.h")
+
+PAT_OK = 0
+STATUS = {0: "PAT_OK", 1: "PAT_ERR_INVALID_ARG", 2: "PAT_ERR_UNSUPPORTED", 3: "PAT_ERR_WORKSPACE",
+          4: "PAT_ERR_HIP", 5: "PAT_ERR_INTERNAL"}
+PRECISION = {"f64": 0, "f32": 1, "bf16grid": 2}
+
+
+class PatError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pat_geometry(ctypes.Structure):
+    _fields_ = [("ndim", c_int32), ("nx", c_int32 * 2), ("nt", c_int32), ("nz", c_int32),
+                ("dx", c_double), ("dt", c_double), ("dz", c_double), ("vs", c_double),
+                ("c", c_double), ("K", c_double), ("alpha", c_double), ("precision", c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0808_3510_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = c_void_p
+        sig = {
+            "pat_plan_create": (c_int32, [POINTER(pat_geometry), POINTER(c_void_p)]),
+            "pat_plan_sizes": (c_int32, [vp, POINTER(c_size_t), POINTER(c_size_t)]),
+            "pat_plan_upload": (c_int32, [vp, vp, vp]),
+            "pat_reconstruct": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_reconstruct_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_forward": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_forward_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_batched_workspace_size": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_size_t)]),
+            "pat_reconstruct_batched": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p),
+                                                  POINTER(c_void_p), vp, vp]),
+            "pat_nufft2_lines": (c_int32, [vp, vp, vp, vp]),
+            "pat_plan_set_timing": (c_int32, [vp, c_int32]),
+            "pat_plan_stage_times": (c_int32, [vp, c_int32, POINTER(c_char_p), POINTER(c_float),
+                                               POINTER(c_int32)]),
+            "pat_plan_destroy": (None, [vp]),
+            "pat_status_string": (c_char_p, [c_int32]),
+            "pat_last_error": (c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Every function the public header declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(pat_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != PAT_OK:
+        raise PatError(status, lib().pat_last_error().decode())
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points (pointers as Python ints)
+
+def pat_plan_create(geom: pat_geometry) -> int:
+    ptr = c_void_p()
+    _check(lib().pat_plan_create(byref(geom), byref(ptr)))
+    return ptr.value
+
+
+def pat_plan_sizes(plan: int) -> tuple[int, int]:
+    t, w = c_size_t(), c_size_t()
+    _check(lib().pat_plan_sizes(plan, byref(t), byref(w)))
+    return t.value, w.value
+
+
+def pat_plan_upload(plan: int, table: int, stream: int):
+    _check(lib().pat_plan_upload(plan, table, stream))
+
+
+def pat_reconstruct(plan, p, f, ws, stream):
+    _check(lib().pat_reconstruct(plan, p, f, ws, stream))
+
+
+def pat_reconstruct_adjoint(plan, f, p, ws, stream):
+    _check(lib().pat_reconstruct_adjoint(plan, f, p, ws, stream))
+
+
+def pat_forward(plan, f, p, ws, stream):
+    _check(lib().pat_forward(plan, f, p, ws, stream))
+
+
+def pat_forward_adjoint(plan, p, f, ws, stream):
+    _check(lib().pat_forward_adjoint(plan, p, f, ws, stream))
+
+
+def _ptr_array(vals):
+    return (c_void_p * len(vals))(*vals)
+
+
+def pat_batched_workspace_size(plans) -> int:
+    w = c_size_t()
+    _check(lib().pat_batched_workspace_size(len(plans), _ptr_array(plans), byref(w)))
+    return w.value
+
+
+def pat_reconstruct_batched(plans, ps, fs, ws, stream):
+    _check(lib().pat_reconstruct_batched(len(plans), _ptr_array(plans), _ptr_array(ps), _ptr_array(fs),
+                                         ws, stream))
+
+
+def pat_nufft2_lines(plan, grid, out, stream):
+    _check(lib().pat_nufft2_lines(plan, grid, out, stream))
+
+
+def pat_plan_set_timing(plan, on: bool):
+    _check(lib().pat_plan_set_timing(plan, 1 if on else 0))
+
+
+def pat_plan_stage_times(plan, cap: int = 64):
+    names = (c_char_p * cap)()
+    ms = (c_float * cap)()
+    n = c_int32()
+    _check(lib().pat_plan_stage_times(plan, cap, names, ms, byref(n)))
+    return [(names[i].decode(), float(ms[i])) for i in range(min(n.value, cap))]
+
+
+def pat_plan_destroy(plan):
+    lib().pat_plan_destroy(plan)
+
+
+def pat_status_string(s: int) -> str:
+    return lib().pat_status_string(s).decode()
+
+
+def pat_last_error() -> str:
+    return lib().pat_last_error().decode()
+
+
+# --------------------------------------------------------------------------
+
+def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, precision="f32") -> pat_geometry:
+    g = pat_geometry()
+    g.ndim = 2 if n2 == 1 else 3
+    g.nx[0], g.nx[1] = int(n1), int(n2)
+    g.nt, g.nz = int(nt), int(nz)
+    g.dx, g.dt, g.dz, g.vs = float(dx), float(dt), float(dz), float(vs)
+    g.c, g.K, g.alpha = float(c), float(K), float(alpha)
+    g.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    return g
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A plan, its uploaded table and its workspace on one device.
+
+    ``n2 = 1`` selects the 2D line geometry.  Arrays are ``(n1, n2, nt)`` /
+    ``(n1, n2, nz)`` (or ``(n1, nt)`` / ``(n1, nz)`` in 2D), contiguous, float64
+    for ``precision="f64"`` and float32 otherwise.
+    """
+
+    def __init__(self, n1, n2, nt, nz, dx=1.0, dt=1.0, dz=1.0, vs=1.0, c=2.0, K=3.0, alpha=0.0,
+                 precision="f32", device="cuda"):
+        self.geom = make_geometry(n1, n2, nt, nz, dx, dt, dz, vs, c, K, alpha, precision)
+        self.n1, self.n2, self.nt, self.nz = int(n1), int(n2), int(nt), int(nz)
+        self.m = int(round(c * nt))
+        self.lines = (self.n1 // 2 + 1) * self.n2
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.device = torch.device(device)
+        self.ptr = pat_plan_create(self.geom)
+        tb, wb = pat_plan_sizes(self.ptr)
+        self.table = torch.empty(tb, dtype=torch.uint8, device=self.device)
+        pat_plan_upload(self.ptr, self.table.data_ptr(), _stream(self.device))
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        ptr = getattr(self, "ptr", None)
+        if ptr and _lib is not None:
+            _lib.pat_plan_destroy(ptr)
+            self.ptr = None
+
+    # shape handling -------------------------------------------------------
+    def _check(self, x: torch.Tensor, last: int, what: str) -> torch.Tensor:
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{what} must be a torch tensor")
+        if x.device != self.device and not (x.device.type == self.device.type and
+                                            (self.device.index is None or x.device.index == self.device.index)):
+            raise ValueError(f"{what} is on {x.device}, plan on {self.device}")
+        if x.dtype != self.dtype:
+            raise TypeError(f"{what} must be {self.dtype}, got {x.dtype}")
+        if x.numel() != self.n1 * self.n2 * last or x.shape[-1] != last or x.shape[0] != self.n1:
+            raise ValueError(f"{what} has shape {tuple(x.shape)}, expected ({self.n1}, {self.n2}, {last})")
+        if not x.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return x
+
+    def _out(self, x: torch.Tensor, last: int) -> torch.Tensor:
+        shape = (self.n1, last) if x.dim() == 2 else (self.n1, self.n2, last)
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    def _call(self, fn, x, last_in, last_out, out=None):
+        self._check(x, last_in, "input")
+        y = self._out(x, last_out) if out is None else self._check(out, last_out, "output")
+        fn(self.ptr, x.data_ptr(), y.data_ptr(), self.ws.data_ptr(), _stream(self.device))
+        return y
+
+    # operators ------------------------------------------------------------
+    def reconstruct(self, p, out=None):
+        """R: detector data -> image."""
+        return self._call(pat_reconstruct, p, self.nt, self.nz, out)
+
+    def reconstruct_adjoint(self, q, out=None):
+        """R^T: image-shaped -> data-shaped."""
+        return self._call(pat_reconstruct_adjoint, q, self.nz, self.nt, out)
+
+    def forward(self, f, out=None):
+        """A: image -> detector data (spectral forward model)."""
+        return self._call(pat_forward, f, self.nz, self.nt, out)
+
+    def forward_adjoint(self, p, out=None):
+        """A^T: data-shaped -> image-shaped."""
+        return self._call(pat_forward_adjoint, p, self.nt, self.nz, out)
+
+    def nufft2_lines(self, grid: torch.Tensor, out=None) -> torch.Tensor:
+        """Stage a3 alone: grid ``(lines, m)`` complex (``(lines, m, 2)``
+        bfloat16 for the bf16 grid) -> ``(lines, nz)`` complex."""
+        if self.precision == "bf16grid":
+            ok = grid.dtype == torch.bfloat16 and tuple(grid.shape) == (self.lines, self.m, 2)
+        else:
+            cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+            ok = grid.dtype == cdt and tuple(grid.shape) == (self.lines, self.m)
+        if not ok or not grid.is_contiguous() or grid.device.type != self.device.type:
+            raise ValueError("grid has the wrong dtype, shape, device or layout")
+        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+        if out is None:
+            out = torch.empty((self.lines, self.nz), dtype=cdt, device=self.device)
+        pat_nufft2_lines(self.ptr, grid.data_ptr(), out.data_ptr(), _stream(self.device))
+        return out
+
+    def set_timing(self, on: bool = True):
+        pat_plan_set_timing(self.ptr, on)
+
+    def stage_times(self):
+        return pat_plan_stage_times(self.ptr)
+
+
+def reconstruct_batched(plans, ps, outs=None, ws=None):
+    """R for several plans in one persistent launch per stage."""
+    if len(plans) != len(ps):
+        raise ValueError("one input per plan")
+    for pl, p in zip(plans, ps):
+        pl._check(p, pl.nt, "input")
+    if outs is None:
+        outs = [pl._out(p, pl.nz) for pl, p in zip(plans, ps)]
+    ptrs = [pl.ptr for pl in plans]
+    need = pat_batched_workspace_size(ptrs)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=plans[0].device)
+    pat_reconstruct_batched(ptrs, [p.data_ptr() for p in ps], [o.data_ptr() for o in outs], ws.data_ptr(),
+                            _stream(plans[0].device))
+    return outs, ws
+
+
+class ReconFn(torch.autograd.Function):
+    """``f = R p`` with ``grad_p = R^T grad_f`` (type-1 spreading)."""
+
+    @staticmethod
+    def forward(ctx, p, plan):
+        ctx.plan = plan
+        return plan.reconstruct(p.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.reconstruct_adjoint(g.contiguous()), None
+
+
+class ForwardFn(torch.autograd.Function):
+    """``p = A f`` (type-1 spreading) with ``grad_f = A^T grad_p`` (type-2)."""
+
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        return plan.forward(f.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.forward_adjoint(g.contiguous()), None
