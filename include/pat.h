@@ -136,19 +136,24 @@ pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t*
 pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p,
                                    void* const* f, void* ws, void* stream);
 
-/* Stage a3 alone (type-2 interpolation + weight) on the half spectrum:
- * grid: ((nx[0]/2+1)*nx[1], c*nt) complex oversampled line spectra in the
- * plan's grid storage (interleaved re,im; float, double or bf16 pairs),
- * as produced by a2 (line (k1, k2) at row k1*nx[1] + k2, k2 in DFT order);
- * out: ((nx[0]/2+1)*nx[1], nz) complex in the plan's element type, l in DFT
- * order, already scaled by 1/(nx[0] nx[1] nz). */
+/* Stage a3 alone (type-2 interpolation + weight) on the half spectrum.
+ * grid: (lines, c*nt) complex, lines = (nx[0]/2+1)*nx[1], line (k1, k2) at
+ *   row k1*nx[1] + k2 (k2 in DFT order), interleaved (re, im) in the plan's
+ *   grid storage (double, float or bf16 pairs).  Row j of a line holding the
+ *   detector-DFT values G[n] is what stage a2 writes (eq. nufft-c, centred):
+ *     U[j] = sum_n G[n] e^{alpha K} / (I0(alpha K) Psi(2 pi n/nt - pi))
+ *                   * exp(-2 pi i j (n - nt/2) / (c nt)).
+ * out: (lines, nz) complex in the plan's element type, l in DFT order:
+ *   W_{k,l} T[G](nu_{k,l}) / (nx[0] nx[1] nz), with the l = 0 and l = -nz/2
+ *   conventions of pat_reconstruct. */
 pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream);
 
-/* Per-stage timing of the plan's last transform.  pat_plan_set_timing(plan,1)
- * makes later transforms record a hipEvent before and after every kernel on
- * their stream; pat_plan_stage_times() then synchronises on the last event
- * and writes up to `cap` entries: names[i] (static strings) and ms[i].
- * Returns the number of stages through *count. */
+/* Per-kernel timing.  pat_plan_set_timing(plan, 1) makes later transforms of
+ * this plan (and batched calls whose first plan it is) record a hipEvent
+ * before and after every kernel on their stream.  pat_plan_stage_times()
+ * synchronises on those events, writes up to `cap` records in launch order
+ * (names[i]: static strings, ms[i]: kernel time) and the number of records
+ * through *count, then forgets them; records accumulate until then. */
 pat_status pat_plan_set_timing(pat_plan* plan, int32_t on);
 pat_status pat_plan_stage_times(pat_plan* plan, int32_t cap, const char** names, float* ms,
                                 int32_t* count);

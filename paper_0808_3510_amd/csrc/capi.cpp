@@ -64,12 +64,11 @@ class EventTimer : public pat::StageTimer {
   size_t used_ = 0;
 };
 
+// Records accumulate over calls until pat_plan_stage_times() reads them.
 EventTimer* timer_of(pat_plan* p) {
   if (!p->timing) return nullptr;
   if (!p->timer) p->timer = new (std::nothrow) EventTimer();
-  EventTimer* t = static_cast<EventTimer*>(p->timer);
-  if (t) t->reset();
-  return t;
+  return static_cast<EventTimer*>(p->timer);
 }
 
 pat_status check_plan(const pat_plan* p) {
@@ -224,6 +223,7 @@ pat_status pat_plan_stage_times(pat_plan* plan, int32_t cap, const char** names,
     if (ms) ms[i] = t->ms(i);
   }
   *count = n;
+  t->reset();
   return PAT_OK;
 }
 
