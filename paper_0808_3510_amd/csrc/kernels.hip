@@ -1,7 +1,8 @@
 // CDNA4 (gfx950) kernels of the NUFFT-based planar photoacoustic
 // reconstruction.  Every kernel runs 256-thread workgroups over a list of work
-// items (instance, tile or line); items come either one per workgroup or from
-// a device work counter drained by a persistent grid (batched form).
+// items (instance, tile or group of lines); items come either one per
+// workgroup or from a device work counter drained by a persistent grid (the
+// batched form).
 //
 // Stages (see pat.h for the operators they compose):
 //   k_tr_x1_r2c   DFT over the first detector axis, real input, half spectrum
@@ -15,8 +16,10 @@
 //   k_line_spread its transpose (type-1), gathered per grid cell over the
 //                 monotone node list of the line: no atomics, deterministic
 //
-// All uniform FFTs are in-place decimation-in-frequency mixed-radix transforms
-// in LDS; bin k ends at position perm[k] (a table built by the host plan).
+// Uniform FFTs are in-place decimation-in-frequency mixed-radix transforms in
+// LDS; bin k ends at position perm[k] (a table built by the host plan).  Two
+// instantiations exist: radices 2/4/8 with shift arithmetic (all lengths
+// powers of two), and the general one (odd primes up to 23).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -69,6 +72,17 @@ __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ __forceinline__ void m_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
 
+template <typename T>
+struct Deg;
+template <>
+struct Deg<float> {
+  static constexpr int v = kPolyDegF;
+};
+template <>
+struct Deg<double> {
+  static constexpr int v = kPolyDegD;
+};
+
 // Storage of the oversampled grid: the compute type itself, or bf16 pairs.
 template <typename T, typename G>
 struct GridIO;
@@ -103,10 +117,11 @@ struct GridIO<float, bf2> {
 // length Li (L, L/R_1, ...): butterfly j of a block reads x[j + r*Li/R],
 // forms the R-point DFT, multiplies output d by exp(-2 pi i j d / Li) and
 // writes it back to position j + d*Li/R.  Transform b's element e lives at
-// buf[b*bs + e*es]; threads are mapped batch-fastest.
+// buf[b*bs + e*es].  BF selects the thread mapping: butterfly index fastest
+// (contiguous lines) or transform index fastest (column tiles).
 
 template <typename T, int R>
-__device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* __restrict__ tw, int L) {
+__device__ __forceinline__ void dft_pow2(cx<T>* v) {
   if constexpr (R == 2) {
     cx<T> a = v[0], b = v[1];
     v[0] = cadd(a, b);
@@ -118,17 +133,17 @@ __device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* __restrict__ tw
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, d13);
     v[3] = csub(d02, d13);
-  } else if constexpr (R == 8) {
+  } else {
+    static_assert(R == 8, "radix");
     const T h = T(0.70710678118654752440084436210484904);
-    // even / odd 4-point DFTs
     cx<T> e[4] = {v[0], v[2], v[4], v[6]};
     cx<T> o[4] = {v[1], v[3], v[5], v[7]};
-    dft_small<T, 4>(e, tw, L);
-    dft_small<T, 4>(o, tw, L);
+    dft_pow2<T, 4>(e);
+    dft_pow2<T, 4>(o);
     // o[d] *= exp(-2 pi i d / 8)
-    cx<T> o1 = mk(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
-    cx<T> o2 = cmi(o[2]);
-    cx<T> o3 = mk(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+    const cx<T> o1 = mk(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+    const cx<T> o2 = cmi(o[2]);
+    const cx<T> o3 = mk(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
     v[0] = cadd(e[0], o[0]);
     v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], o1);
@@ -137,73 +152,133 @@ __device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* __restrict__ tw
     v[6] = csub(e[2], o2);
     v[3] = cadd(e[3], o3);
     v[7] = csub(e[3], o3);
-  } else {
-    // odd prime: direct R-point DFT with roots from the L-point table
-    const int step = L / R;
-    cx<T> w[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) w[q] = tw[q * step];
-    cx<T> y[R];
-#pragma unroll
-    for (int d = 0; d < R; ++d) {
-      cx<T> acc = v[0];
-#pragma unroll
-      for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], w[(r * d) % R]));
-      y[d] = acc;
-    }
-#pragma unroll
-    for (int d = 0; d < R; ++d) v[d] = y[d];
   }
 }
 
+// Odd-prime butterfly: the R inputs are held in registers, outputs are formed
+// one at a time (roots exp(-2 pi i q / R) read from the L-point table at a
+// workgroup-uniform index) and written back, so no indexed local array is
+// needed.
 template <typename T, int R>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>* __restrict__ tw,
-                                          int nb, int bs, int es) {
+__device__ __forceinline__ void bfly_prime(cx<T>* p, int st, int j, int tws, const cx<T>* __restrict__ tw,
+                                           int L) {
+  cx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = p[r * st];
+  const int step = L / R;
+  for (int d = 0; d < R; ++d) {
+    cx<T> acc = v[0];
+    int q = 0;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      q += d;
+      if (q >= R) q -= R;
+      acc = cadd(acc, cmul(v[r], tw[q * step]));
+    }
+    if (d) acc = cmul(acc, tw[j * d * tws]);
+    p[d * st] = acc;
+  }
+}
+
+template <typename T, int R, bool P2, bool BF>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>* __restrict__ tw, int nb,
+                                          int bs, int es) {
   const int sub = Li / R;
   const int tws = L / Li;
-  const int total = (L / R) * nb;
+  const int nbf = L / R;
+  const int total = nbf * nb;
+  int lsub = 0, lnbf = 0, lnb = 0;
+  if constexpr (P2) {
+    lsub = __builtin_ctz((unsigned)sub);
+    lnbf = __builtin_ctz((unsigned)nbf);
+    lnb = __builtin_ctz((unsigned)nb);
+  }
   for (int id = threadIdx.x; id < total; id += kBlock) {
-    const int bf = id / nb;
-    const int b = id - bf * nb;
-    const int blk = bf / sub;
-    const int j = bf - blk * sub;
+    int b, bf;
+    if constexpr (BF) {
+      if constexpr (P2) {
+        bf = id & (nbf - 1);
+        b = id >> lnbf;
+      } else {
+        b = id / nbf;
+        bf = id - b * nbf;
+      }
+    } else {
+      if constexpr (P2) {
+        b = id & (nb - 1);
+        bf = id >> lnb;
+      } else {
+        bf = id / nb;
+        b = id - bf * nb;
+      }
+    }
+    int blk, j;
+    if constexpr (P2) {
+      blk = bf >> lsub;
+      j = bf & (sub - 1);
+    } else {
+      blk = bf / sub;
+      j = bf - blk * sub;
+    }
     cx<T>* p = buf + b * bs + (blk * Li + j) * es;
     const int st = sub * es;
-    cx<T> v[R];
+    if constexpr (R == 2 || R == 4 || R == 8) {
+      cx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = p[r * st];
-    dft_small<T, R>(v, tw, L);
+      for (int r = 0; r < R; ++r) v[r] = p[r * st];
+      dft_pow2<T, R>(v);
 #pragma unroll
-    for (int d = 1; d < R; ++d) v[d] = cmul(v[d], tw[j * d * tws]);
+      for (int d = 1; d < R; ++d) v[d] = cmul(v[d], tw[j * d * tws]);
 #pragma unroll
-    for (int r = 0; r < R; ++r) p[r * st] = v[r];
+      for (int r = 0; r < R; ++r) p[r * st] = v[r];
+    } else {
+      bfly_prime<T, R>(p, st, j, tws, tw, L);
+    }
   }
 }
 
-template <typename T>
-__device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw_all, int nb, int bs,
-                        int es) {
+template <typename T, bool P2, bool BF>
+__device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw_all, int nb, int bs, int es) {
   const cx<T>* tw = tw_all + d.tw;
   const int L = d.L;
   int Li = L;
   for (int s = 0; s < d.nst; ++s) {
     const int R = d.rad[s];
-    switch (R) {
-      case 2: fft_stage<T, 2>(buf, Li, L, tw, nb, bs, es); break;
-      case 3: fft_stage<T, 3>(buf, Li, L, tw, nb, bs, es); break;
-      case 4: fft_stage<T, 4>(buf, Li, L, tw, nb, bs, es); break;
-      case 5: fft_stage<T, 5>(buf, Li, L, tw, nb, bs, es); break;
-      case 7: fft_stage<T, 7>(buf, Li, L, tw, nb, bs, es); break;
-      case 8: fft_stage<T, 8>(buf, Li, L, tw, nb, bs, es); break;
-      case 11: fft_stage<T, 11>(buf, Li, L, tw, nb, bs, es); break;
-      case 13: fft_stage<T, 13>(buf, Li, L, tw, nb, bs, es); break;
-      case 17: fft_stage<T, 17>(buf, Li, L, tw, nb, bs, es); break;
-      case 19: fft_stage<T, 19>(buf, Li, L, tw, nb, bs, es); break;
-      case 23: fft_stage<T, 23>(buf, Li, L, tw, nb, bs, es); break;
-      default: break;  // the host plan only emits the radices above
+    if constexpr (P2) {
+      if (R == 8) fft_stage<T, 8, P2, BF>(buf, Li, L, tw, nb, bs, es);
+      else if (R == 4) fft_stage<T, 4, P2, BF>(buf, Li, L, tw, nb, bs, es);
+      else fft_stage<T, 2, P2, BF>(buf, Li, L, tw, nb, bs, es);
+    } else {
+      switch (R) {
+        case 2: fft_stage<T, 2, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 3: fft_stage<T, 3, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 4: fft_stage<T, 4, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 5: fft_stage<T, 5, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 7: fft_stage<T, 7, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 8: fft_stage<T, 8, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 11: fft_stage<T, 11, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 13: fft_stage<T, 13, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 17: fft_stage<T, 17, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 19: fft_stage<T, 19, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 23: fft_stage<T, 23, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        default: break;  // the host plan only emits the radices above
+      }
     }
     __syncthreads();
     Li /= R;
+  }
+}
+
+// quotient and remainder by a length that is a power of two in the P2 path
+template <bool P2>
+__device__ __forceinline__ void divmod(int e, int L, int* q, int* r) {
+  if constexpr (P2) {
+    const int s = __builtin_ctz((unsigned)L);
+    *q = e >> s;
+    *r = e & (L - 1);
+  } else {
+    *q = e / L;
+    *r = e - *q * L;
   }
 }
 
@@ -212,6 +287,8 @@ __device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ 
 //   Psi_hat(u) I0(alpha K) / (2 e^{alpha K}) = e^{alpha (s - K)} (1 - e^{-2 alpha s}) / (2 s)
 // (the transform of Section 3.2 with the large factor e^{alpha K} / I0(alpha K)
 // moved into the deconvolution table), limit alpha e^{-alpha K} at s -> 0.
+// Direct evaluation; the tap loops normally use the per-tap polynomials the
+// host plan fitted to this function instead.
 
 template <typename T>
 __device__ __forceinline__ T kb_phi(T u, T K, T alpha) {
@@ -226,6 +303,16 @@ __device__ __forceinline__ T kb_phi(T u, T K, T alpha) {
     v = alpha * (T(1) - as + T(2) / T(3) * as * as);
   }
   return m_exp(alpha * (s - K)) * v;
+}
+
+// tap t of a node whose offset is x = 2 (delta - cK) + 1, from the table
+template <typename T>
+__device__ __forceinline__ T tap_poly(const T* __restrict__ c, T x) {
+  constexpr int D = Deg<T>::v;
+  T w = c[D];
+#pragma unroll
+  for (int d = D - 1; d >= 0; --d) w = w * x + c[d];
+  return w;
 }
 
 // Node position on the oversampled grid: x = c nu, first tap j0 = floor(x - cK) + 1,
@@ -251,22 +338,36 @@ __device__ __forceinline__ cx<T> phase_mpi(double nu) {
   return mk(c, -s);
 }
 
-// sum_t phi((delta - t)/c) U[(j0 + t) mod m] times exp(-i pi nu)
+// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m]
 template <typename T>
-__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, int taps, double nu, const Inst& I,
-                                             T cinv, T K, T alpha) {
+__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, const Inst& I) {
   const NodePos np = node_pos(nu, I.c, I.ck);
-  const T delta = (T)np.delta;
   int jm = np.j0 % m;
   if (jm < 0) jm += m;
+  const int taps = I.taps;
   cx<T> acc = mk(T(0), T(0));
-  for (int t = 0; t < taps; ++t) {
-    const T w = kb_phi<T>((delta - T(t)) * cinv, K, alpha);
-    const cx<T> g = U[jm];
-    acc.x += w * g.x;
-    acc.y += w * g.y;
-    ++jm;
-    if (jm == m) jm = 0;
+  if (I.poly) {
+    const T x = (T)(2.0 * (np.delta - I.ck) + 1.0);
+    const T* pc = static_cast<const T*>(I.poly_c);
+    constexpr int D1 = Deg<T>::v + 1;
+    for (int t = 0; t < taps; ++t) {
+      const T w = tap_poly<T>(pc + t * D1, x);
+      const cx<T> g = U[jm];
+      acc.x += w * g.x;
+      acc.y += w * g.y;
+      ++jm;
+      if (jm == m) jm = 0;
+    }
+  } else {
+    const T delta = (T)np.delta, cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
+    for (int t = 0; t < taps; ++t) {
+      const T w = kb_phi<T>((delta - T(t)) * cinv, K, alpha);
+      const cx<T> g = U[jm];
+      acc.x += w * g.x;
+      acc.y += w * g.y;
+      ++jm;
+      if (jm == m) jm = 0;
+    }
   }
   return cmul(acc, phase_mpi<T>(nu));
 }
@@ -325,7 +426,7 @@ extern __shared__ __align__(16) unsigned char pat_smem[];
 // axis) by the full transform length; lane -> sample, so global accesses are
 // contiguous runs of tb elements.
 
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
@@ -338,24 +439,25 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]);
   const int L = I.n1;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    const int x = e / tb;
-    const int t = t0 + (e - x * tb);
+    int x, b;
+    divmod<true>(e, tb, &x, &b);
+    const int t = t0 + b;
     const T v = t < len ? in[((size_t)x * I.n2 + x2) * len + t] : T(0);
     buf[e] = mk(v, T(0));
   }
   __syncthreads();
-  fft_lds<T>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
-    const int k = e / tb;
-    const int b = e - k * tb;
+    int k, b;
+    divmod<true>(e, tb, &k, &b);
     const int t = t0 + b;
     if (t < len) out[((size_t)k * I.n2 + x2) * len + t] = buf[perm[k] * tb + b];
   }
   PAT_END_ITEM
 }
 
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
@@ -368,17 +470,18 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   const int L = I.n2;
   const bool inv = a.mode != 0;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    const int x = e / tb;
-    const int t = t0 + (e - x * tb);
-    cx<T> v = t < len ? io[((size_t)k1 * L + x) * len + t] : mk(T(0), T(0));
+    int x, b;
+    divmod<true>(e, tb, &x, &b);
+    const int t = t0 + b;
+    const cx<T> v = t < len ? io[((size_t)k1 * L + x) * len + t] : mk(T(0), T(0));
     buf[e] = inv ? cconj(v) : v;
   }
   __syncthreads();
-  fft_lds<T>(buf, I.f2, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f2, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f2.perm;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    const int k = e / tb;
-    const int b = e - k * tb;
+    int k, b;
+    divmod<true>(e, tb, &k, &b);
     const int t = t0 + b;
     if (t < len) {
       const cx<T> v = buf[perm[k] * tb + b];
@@ -390,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 
 // Inverse DFT over the first axis from bins 0..n1/2 (the others are the
 // complex conjugates of their mirror bins), keeping the real part.
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
@@ -404,19 +507,20 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   const int L = I.n1;
   const int half = L / 2;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    const int k = e / tb;
-    const int t = t0 + (e - k * tb);
+    int k, b;
+    divmod<true>(e, tb, &k, &b);
+    const int t = t0 + b;
     const int src = k <= half ? k : L - k;
-    cx<T> v = t < len ? in[((size_t)src * I.n2 + x2) * len + t] : mk(T(0), T(0));
+    const cx<T> v = t < len ? in[((size_t)src * I.n2 + x2) * len + t] : mk(T(0), T(0));
     // inverse transform as conj(FFT(conj(.))); mirrored bins are conjugated once more
     buf[e] = k <= half ? cconj(v) : v;
   }
   __syncthreads();
-  fft_lds<T>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    const int x = e / tb;
-    const int b = e - x * tb;
+    int x, b;
+    divmod<true>(e, tb, &x, &b);
     const int t = t0 + b;
     if (t < len) out[((size_t)x * I.n2 + x2) * len + t] = buf[perm[x] * tb + b].x;
   }
@@ -424,33 +528,37 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Line stages: one frequency line (k1, k2) per work item.
+// Line stages: a group of consecutive frequency lines (k1, k2) per work item.
 
-__device__ __forceinline__ void line_freqs(const Inst& I, int line, double* Ak) {
+__device__ __forceinline__ double line_ak(const Inst& I, int line) {
   const int k1 = line / I.n2;
   const int k2i = line - k1 * I.n2;
   const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
-  *Ak = I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
+  return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
 }
 
 // DFT of length nz along each line, in place.
-template <typename T>
+template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
   const int L = I.nz;
-  cx<T>* io = static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * L;
+  const int line0 = li * I.lpw_z;
+  const int nl = min(I.lpw_z, I.lines - line0);
+  cx<T>* io = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * L;
   const bool inv = a.mode != 0;
-  for (int j = threadIdx.x; j < L; j += kBlock) {
-    const cx<T> v = io[j];
-    buf[j] = inv ? cconj(v) : v;
+  for (int e = threadIdx.x; e < nl * L; e += kBlock) {
+    const cx<T> v = io[e];
+    buf[e] = inv ? cconj(v) : v;
   }
   __syncthreads();
-  fft_lds<T>(buf, I.fz, static_cast<const cx<T>*>(I.tw), 1, 0, 1);
+  fft_lds<T, P2, true>(buf, I.fz, static_cast<const cx<T>*>(I.tw), nl, L, 1);
   const int32_t* perm = I.perm + I.fz.perm;
-  for (int j = threadIdx.x; j < L; j += kBlock) {
-    const cx<T> v = buf[perm[j]];
-    io[j] = inv ? cconj(v) : v;
+  for (int e = threadIdx.x; e < nl * L; e += kBlock) {
+    int b, j;
+    divmod<P2>(e, L, &b, &j);
+    const cx<T> v = buf[b * L + perm[j]];
+    io[e] = inv ? cconj(v) : v;
   }
   PAT_END_ITEM
 }
@@ -458,43 +566,55 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
 // a2: u_n = G_n s_n placed at (n - nt/2) mod m, zeros elsewhere, FFT of length m.
 // The centring turns the per-tap factor exp(i pi j / c) of eq. (nufft-a) into
 // a shift, leaving only exp(-i pi nu) per node.
-template <typename T, typename G>
+template <typename T, typename G, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nt = I.nt;
-  const cx<T>* g = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nt;
+  const int line0 = li * I.lpw_m;
+  const int nl = min(I.lpw_m, I.lines - line0);
+  const cx<T>* g = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt;
   G* grid = static_cast<G*>(a.out[inst_]);
   const T* sn = static_cast<const T*>(I.sn);
-  for (int j = threadIdx.x; j < m; j += kBlock) {
+  for (int e = threadIdx.x; e < nl * m; e += kBlock) {
+    int b, j;
+    divmod<P2>(e, m, &b, &j);
     int n = j + nt / 2;
     if (n >= m) n -= m;
-    buf[j] = n < nt ? cscl(g[n], sn[n]) : mk(T(0), T(0));
+    buf[e] = n < nt ? cscl(g[(size_t)b * nt + n], sn[n]) : mk(T(0), T(0));
   }
   __syncthreads();
-  fft_lds<T>(buf, I.fm, static_cast<const cx<T>*>(I.tw), 1, 0, 1);
+  fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
-  for (int j = threadIdx.x; j < m; j += kBlock) GridIO<T, G>::st(grid, (size_t)li * m + j, buf[perm[j]]);
+  for (int e = threadIdx.x; e < nl * m; e += kBlock) {
+    int b, j;
+    divmod<P2>(e, m, &b, &j);
+    GridIO<T, G>::st(grid, (size_t)line0 * m + e, buf[b * m + perm[j]]);
+  }
   PAT_END_ITEM
 }
 
 // transpose of a2: X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
-template <typename T, typename G>
+template <typename T, typename G, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nt = I.nt;
+  const int line0 = li * I.lpw_m;
+  const int nl = min(I.lpw_m, I.lines - line0);
   const G* grid = static_cast<const G*>(a.in[inst_]);
-  cx<T>* x = static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt;
+  cx<T>* x = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt;
   const T* sn = static_cast<const T*>(I.sn);
-  for (int j = threadIdx.x; j < m; j += kBlock) buf[j] = cconj(GridIO<T, G>::ld(grid, (size_t)li * m + j));
+  for (int e = threadIdx.x; e < nl * m; e += kBlock) buf[e] = cconj(GridIO<T, G>::ld(grid, (size_t)line0 * m + e));
   __syncthreads();
-  fft_lds<T>(buf, I.fm, static_cast<const cx<T>*>(I.tw), 1, 0, 1);
+  fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
-  for (int n = threadIdx.x; n < nt; n += kBlock) {
+  for (int e = threadIdx.x; e < nl * nt; e += kBlock) {
+    int b, n;
+    divmod<P2>(e, nt, &b, &n);
     int pos = n - nt / 2;
     if (pos < 0) pos += m;
-    x[n] = cscl(cconj(buf[perm[pos]]), sn[n]);
+    x[e] = cscl(cconj(buf[b * m + perm[pos]]), sn[n]);
   }
   PAT_END_ITEM
 }
@@ -507,14 +627,17 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz;
+  const int line0 = li * I.lpw_i;
+  const int nl = min(I.lpw_i, I.lines - line0);
   const G* grid = static_cast<const G*>(a.in[inst_]);
-  cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nz;
-  for (int j = threadIdx.x; j < m; j += kBlock) buf[j] = GridIO<T, G>::ld(grid, (size_t)li * m + j);
+  cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
+  for (int e = threadIdx.x; e < nl * m; e += kBlock) buf[e] = GridIO<T, G>::ld(grid, (size_t)line0 * m + e);
   __syncthreads();
-  double Ak;
-  line_freqs(I, li, &Ak);
-  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
-  for (int il = threadIdx.x; il < nz; il += kBlock) {
+  for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
+    const int b = e / nz;
+    const int il = e - b * nz;
+    const cx<T>* U = buf + b * m;
+    const double Ak = line_ak(I, line0 + b);
     const int l = 2 * il < nz ? il : il - nz;
     const double nup = sqrt(Ak + I.b * (double)l * (double)l);
     cx<T> v;
@@ -524,39 +647,27 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
       } else {
         const double w = I.wcoef * (double)(l < 0 ? -l : l) / nup * I.scale;
         if (2 * l == -nz) {
-          v = cadd(interp_eval<T>(buf, m, I.taps, -nup, I, cinv, K, alpha),
-                   interp_eval<T>(buf, m, I.taps, nup, I, cinv, K, alpha));
+          v = cadd(interp_eval<T>(U, m, -nup, I), interp_eval<T>(U, m, nup, I));
           v = cscl(v, T(0.5 * w));
         } else {
-          v = cscl(interp_eval<T>(buf, m, I.taps, l > 0 ? nup : -nup, I, cinv, K, alpha), T(w));
+          v = cscl(interp_eval<T>(U, m, l > 0 ? nup : -nup, I), T(w));
         }
       }
     } else {
-      v = cadd(interp_eval<T>(buf, m, I.taps, nup, I, cinv, K, alpha),
-               interp_eval<T>(buf, m, I.taps, -nup, I, cinv, K, alpha));
+      v = cadd(interp_eval<T>(U, m, nup, I), interp_eval<T>(U, m, -nup, I));
       v = cscl(v, T(0.5 * I.scale));
     }
-    out[il] = v;
+    out[e] = v;
   }
   PAT_END_ITEM
 }
 
-// first index i in [0, n) with key[i] >= v (n if none)
-__device__ __forceinline__ int lower_bound_i(const int* key, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (key[mid] < v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // a6: type-1 spreading, the transpose of k_line_interp's sum.  The line's
 // nodes are listed in increasing order (they are monotone in l by
-// construction), each with its first tap j0 and value; every grid cell then
-// gathers the nodes whose 2cK-tap window covers it (binary search on j0),
-// for each periodic image of the cell.
+// construction) with their first tap j0, polynomial offset x and value.  A
+// start table maps every first-tap index v to the first node with j0 >= v, so
+// grid cell j (and each of its periodic images j + q m) gathers exactly the
+// nodes with j0 in (j - taps, j], in node order: no atomics, deterministic.
 //   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
 //     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
 //     whose value feeds both -nu+ and +nu+.
@@ -566,17 +677,23 @@ template <typename T, typename G>
 __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz, taps = I.taps;
+  constexpr int D1 = Deg<T>::v + 1;
   const int nn = a.mode == 0 ? nz + 1 : nz + 2;
   cx<T>* val = reinterpret_cast<cx<T>*>(pat_smem);
-  T* dl = reinterpret_cast<T*>(val + nn);
-  int* j0s = reinterpret_cast<int*>(dl + nn);
+  T* xs = reinterpret_cast<T*>(val + nn);
+  T* coef = xs + nn;
+  int* j0s = reinterpret_cast<int*>(coef + taps * D1);
+  int* start = j0s + nn;
   const cx<T>* F = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
   G* grid = static_cast<G*>(a.out[inst_]);
-  double Ak;
-  line_freqs(I, li, &Ak);
+  const double Ak = line_ak(I, li);
   const int half = nz / 2;
+  if (I.poly) {
+    const T* pc = static_cast<const T*>(I.poly_c);
+    for (int i = threadIdx.x; i < taps * D1; i += kBlock) coef[i] = pc[i];
+  }
   for (int i = threadIdx.x; i < nn; i += kBlock) {
-    double nu, coef;
+    double nu, cf;
     cx<T> q;
     if (a.mode == 0) {
       const int l = i < nz ? i - half : half;
@@ -585,13 +702,13 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
       q = F[lm];
       if (i == nz) {
         nu = nup;
-        coef = 0.5 * I.wcoef * (double)half / nup;
+        cf = 0.5 * I.wcoef * (double)half / nup;
       } else {
         nu = l > 0 ? nup : (l < 0 ? -nup : 0.0);
-        coef = l == 0 ? 0.0 : I.wcoef * (double)(l < 0 ? -l : l) / nup;
-        if (l == -half) coef *= 0.5;
+        cf = l == 0 ? 0.0 : I.wcoef * (double)(l < 0 ? -l : l) / nup;
+        if (l == -half) cf *= 0.5;
       }
-      coef *= I.scale;
+      cf *= I.scale;
     } else {
       int mp;
       double sg;
@@ -606,29 +723,49 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
       nu = sg * nup;
       q = F[mp];
       if (mp != 0 && mp != half) q = cadd(q, F[nz - mp]);
-      coef = 0.5 * I.scale;
+      cf = 0.5 * I.scale;
     }
     const NodePos np = node_pos(nu, I.c, I.ck);
-    val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(coef));
-    dl[i] = (T)np.delta;
+    val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
+    xs[i] = (T)(2.0 * (np.delta - I.ck) + 1.0);
     j0s[i] = np.j0;
   }
   __syncthreads();
-  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
   const int jlo = j0s[0];
-  const int jhi = j0s[nn - 1] + taps - 1;
+  int span = j0s[nn - 1] - jlo + 1;
+  span = span < I.span_max ? span : I.span_max;
+  for (int i = threadIdx.x; i < nn; i += kBlock) {
+    const int v0 = (i == 0 ? jlo : j0s[i - 1] + 1) - jlo;
+    const int v1 = j0s[i] - jlo;
+    for (int v = v0; v <= v1 && v < span; ++v) start[v] = i;
+  }
+  if (threadIdx.x == 0) start[span] = nn;
+  __syncthreads();
+  const int jhi = jlo + span - 1 + taps - 1;
+  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha), ckh = T(I.ck - 0.5);
   for (int j = threadIdx.x; j < m; j += kBlock) {
     cx<T> acc = mk(T(0), T(0));
     // first periodic image j + q m that can be covered
     int q0 = jlo - j;
     q0 = q0 >= 0 ? (q0 + m - 1) / m : -((-q0) / m);
     for (int jp = j + q0 * m; jp <= jhi; jp += m) {
-      const int lo = lower_bound_i(j0s, nn, jp - taps + 1);
-      const int hi = lower_bound_i(j0s, nn, jp + 1);
-      for (int i = lo; i < hi; ++i) {
-        const T w = kb_phi<T>((dl[i] - T(jp - j0s[i])) * cinv, K, alpha);
-        acc.x += w * val[i].x;
-        acc.y += w * val[i].y;
+      int v0 = jp - taps + 1 - jlo;
+      int v1 = jp - jlo;
+      v0 = v0 > 0 ? v0 : 0;
+      v1 = v1 < span - 1 ? v1 : span - 1;
+      if (v0 > v1) continue;
+      const int i1 = start[v1 + 1];
+      for (int i = start[v0]; i < i1; ++i) {
+        const int t = jp - j0s[i];
+        T w;
+        if (I.poly) {
+          w = tap_poly<T>(coef + t * D1, xs[i]);
+        } else {
+          w = kb_phi<T>((ckh + T(0.5) * xs[i] - T(t)) * cinv, K, alpha);
+        }
+        const cx<T> vv = val[i];
+        acc.x += w * vv.x;
+        acc.y += w * vv.y;
       }
     }
     GridIO<T, G>::st(grid, (size_t)li * m + j, acc);
@@ -679,34 +816,39 @@ hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStr
   return e;
 }
 
-enum Items { IT_X1, IT_X2, IT_LINES, IT_C2R };
+enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LINE };
+
+int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 int items_of(const Inst& I, Items kind, bool nz) {
   const int len = nz ? I.nz : I.nt;
-  const int ntile = (len + I.tb - 1) / I.tb;
+  const int ntile = cdiv(len, I.tb);
   switch (kind) {
     case IT_X1: return I.n2 * ntile;
     case IT_X2: return I.n2 > 1 ? I.h1 * ntile : 0;
-    case IT_LINES: return I.lines;
     case IT_C2R: return I.n2 * ntile;
+    case IT_LM: return cdiv(I.lines, I.lpw_m);
+    case IT_LZ: return cdiv(I.lines, I.lpw_z);
+    case IT_LI: return cdiv(I.lines, I.lpw_i);
+    case IT_LINE: return I.lines;
   }
   return 0;
 }
 
-template <typename T, typename G>
+template <typename T, typename G, bool P2>
 struct Runner {
   int n;
   const Inst* h;
   const Inst* const* d;
   uint32_t* counters;
-  int next_counter = 0;
+  int next_counter;
   hipStream_t st;
   StageTimer* tm;
 
   static constexpr size_t cs = sizeof(cx<T>);
+  static constexpr int D1 = Deg<T>::v + 1;
 
-  // in/out pointer of instance i for a stage, from a selector
-  StageArgs base(Items kind, bool nz, int mode) {
+  StageArgs base(Items kind, bool nz, int mode, const void* const* in, void* const* out) {
     StageArgs a;
     a.n = n;
     a.len_nz = nz ? 1 : 0;
@@ -714,6 +856,8 @@ struct Runner {
     a.off[0] = 0;
     for (int i = 0; i < n; ++i) {
       a.inst[i] = d[i];
+      a.in[i] = in[i];
+      a.out[i] = out[i];
       a.off[i + 1] = a.off[i] + items_of(h[i], kind, nz);
     }
     a.total = a.off[n];
@@ -721,97 +865,72 @@ struct Runner {
     return a;
   }
 
-  size_t max_over(size_t (*f)(const Inst&)) const {
-    size_t m = 0;
+  template <typename F>
+  size_t max_over(F f) const {
+    size_t mx = 0;
     for (int i = 0; i < n; ++i) {
       const size_t v = f(h[i]);
-      if (v > m) m = v;
+      if (v > mx) mx = v;
     }
-    return m;
+    return mx;
   }
-
-  static size_t sh_x1(const Inst& I) { return (size_t)I.n1 * I.tb * cs; }
-  static size_t sh_x2(const Inst& I) { return (size_t)I.n2 * I.tb * cs; }
-  static size_t sh_z(const Inst& I) { return (size_t)I.nz * cs; }
-  static size_t sh_m(const Inst& I) { return (size_t)I.m * cs; }
-  static size_t sh_spread(const Inst& I) { return (size_t)(I.nz + 2) * (cs + sizeof(T) + sizeof(int)) + 64; }
 
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
-    StageArgs a = base(IT_X1, nz, 0);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_tr_x1_r2c<T>, "dft_x1", a, max_over(sh_x1), st, tm);
+    StageArgs a = base(IT_X1, nz, 0, in, out);
+    return launch(k_tr_x1_r2c<T, P2>, "dft_x1", a, max_over([](const Inst& I) { return (size_t)I.n1 * I.tb * cs; }),
+                  st, tm);
   }
   hipError_t x2(void* const* io, bool nz, int inv) {
-    StageArgs a = base(IT_X2, nz, inv);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = io[i];
-      a.out[i] = io[i];
-    }
-    return launch(k_tr_x2<T>, inv ? "idft_x2" : "dft_x2", a, max_over(sh_x2), st, tm);
+    StageArgs a = base(IT_X2, nz, inv, io, io);
+    return launch(k_tr_x2<T, P2>, inv ? "idft_x2" : "dft_x2", a,
+                  max_over([](const Inst& I) { return (size_t)I.n2 * I.tb * cs; }), st, tm);
   }
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
-    StageArgs a = base(IT_C2R, nz, 0);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_tr_c2r_k1<T>, "idft_x1_c2r", a, max_over(sh_x1), st, tm);
+    StageArgs a = base(IT_C2R, nz, 0, in, out);
+    return launch(k_tr_c2r_k1<T, P2>, "idft_x1_c2r", a,
+                  max_over([](const Inst& I) { return (size_t)I.n1 * I.tb * cs; }), st, tm);
   }
   hipError_t zfft(void* const* io, int inv) {
-    StageArgs a = base(IT_LINES, true, inv);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = io[i];
-      a.out[i] = io[i];
-    }
-    return launch(k_line_fft<T>, inv ? "idft_z" : "dft_z", a, max_over(sh_z), st, tm);
+    StageArgs a = base(IT_LZ, true, inv, io, io);
+    return launch(k_line_fft<T, P2>, inv ? "idft_z" : "dft_z", a,
+                  max_over([](const Inst& I) { return (size_t)I.lpw_z * I.nz * cs; }), st, tm);
   }
   hipError_t a2(const void* const* in, void* const* out) {
-    StageArgs a = base(IT_LINES, false, 0);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_line_a2<T, G>, "deconv_pad_fft", a, max_over(sh_m), st, tm);
+    StageArgs a = base(IT_LM, false, 0, in, out);
+    return launch(k_line_a2<T, G, P2>, "deconv_pad_fft", a,
+                  max_over([](const Inst& I) { return (size_t)I.lpw_m * I.m * cs; }), st, tm);
   }
   hipError_t a2t(const void* const* in, void* const* out) {
-    StageArgs a = base(IT_LINES, false, 0);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_line_a2t<T, G>, "ifft_pick_deconv", a, max_over(sh_m), st, tm);
+    StageArgs a = base(IT_LM, false, 0, in, out);
+    return launch(k_line_a2t<T, G, P2>, "ifft_pick_deconv", a,
+                  max_over([](const Inst& I) { return (size_t)I.lpw_m * I.m * cs; }), st, tm);
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
-    StageArgs a = base(IT_LINES, true, mode);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_line_interp<T, G>, "interp", a, max_over(sh_m), st, tm);
+    StageArgs a = base(IT_LI, true, mode, in, out);
+    return launch(k_line_interp<T, G>, "interp", a,
+                  max_over([](const Inst& I) { return (size_t)I.lpw_i * I.m * cs; }), st, tm);
   }
   hipError_t spread(const void* const* in, void* const* out, int mode) {
-    StageArgs a = base(IT_LINES, true, mode);
-    for (int i = 0; i < n; ++i) {
-      a.in[i] = in[i];
-      a.out[i] = out[i];
-    }
-    return launch(k_line_spread<T, G>, "spread", a, max_over(sh_spread), st, tm);
+    StageArgs a = base(IT_LINE, true, mode, in, out);
+    return launch(k_line_spread<T, G>, "spread", a, max_over([](const Inst& I) {
+                    const size_t nn = (size_t)I.nz + 2;
+                    return nn * (cs + sizeof(T) + sizeof(int)) + (size_t)I.taps * D1 * sizeof(T) +
+                           ((size_t)I.span_max + 2) * sizeof(int) + 64;
+                  }),
+                  st, tm);
   }
 };
 
-#define PAT_TRY(x)                  \
-  do {                              \
-    hipError_t e_ = (x);            \
+#define PAT_TRY(x)                   \
+  do {                               \
+    hipError_t e_ = (x);             \
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
-template <typename T, typename G>
-hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in,
-                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  Runner<T, G> r{n, h, d, counters, 0, st, tm};
+template <typename T, typename G, bool P2>
+hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
+                    void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
+  Runner<T, G, P2> r{n, h, d, counters, 0, st, tm};
   void* bg[kMaxBatch];
   void* bu[kMaxBatch];
   void* bf[kMaxBatch];
@@ -852,17 +971,30 @@ hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const voi
   return hipSuccess;
 }
 
+bool all_pow2(int n, const Inst* h) {
+  for (int i = 0; i < n; ++i)
+    if (!h[i].pow2) return false;
+  return true;
+}
+
+template <typename T, typename G>
+hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
+                    void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
+  if (all_pow2(n, h)) return run_op_t<T, G, true>(op, n, h, d, in, out, ws, counters, st, tm);
+  return run_op_t<T, G, false>(op, n, h, d, in, out, ws, counters, st, tm);
+}
+
 }  // namespace
 
 hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* in,
                   void* const* out, void* const* ws, uint32_t* counters, hipStream_t stream, StageTimer* timer) {
   switch (prec) {
     case PREC_F64:
-      return run_op_t<double, cx<double>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<double, cx<double>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
     case PREC_F32:
-      return run_op_t<float, cx<float>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<float, cx<float>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
     case PREC_BF16:
-      return run_op_t<float, bf2>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<float, bf2>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
   }
   return hipErrorInvalidValue;
 }
@@ -874,15 +1006,15 @@ hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void
   void* o[1] = {out};
   switch (prec) {
     case PREC_F64: {
-      Runner<double, cx<double>> r{1, &hinst, d, nullptr, 0, stream, timer};
+      Runner<double, cx<double>, false> r{1, &hinst, d, nullptr, 0, stream, timer};
       return r.interp(in, o, 0);
     }
     case PREC_F32: {
-      Runner<float, cx<float>> r{1, &hinst, d, nullptr, 0, stream, timer};
+      Runner<float, cx<float>, false> r{1, &hinst, d, nullptr, 0, stream, timer};
       return r.interp(in, o, 0);
     }
     case PREC_BF16: {
-      Runner<float, bf2> r{1, &hinst, d, nullptr, 0, stream, timer};
+      Runner<float, bf2, false> r{1, &hinst, d, nullptr, 0, stream, timer};
       return r.interp(in, o, 0);
     }
   }

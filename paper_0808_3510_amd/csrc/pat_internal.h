@@ -13,6 +13,10 @@ constexpr int kMaxBatch = 32;    // instances in one batched call
 constexpr int kMaxTaps = 64;     // 2cK
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
+// Degree of the per-tap polynomial that replaces the kernel evaluation
+// (float and double paths).
+constexpr int kPolyDegF = 9;
+constexpr int kPolyDegD = 15;
 
 // One FFT length: in-place decimation-in-frequency mixed-radix factorisation.
 // After the transform the natural-order bin k sits at LDS position perm[k].
@@ -31,7 +35,11 @@ struct Inst {
   int32_t lines;              // h1 * n2 frequency lines
   int32_t taps;               // 2cK
   int32_t tb;                 // batch width of the transverse tiles
-  int32_t pad_;
+  int32_t poly;               // 1: per-tap polynomial table valid, 0: direct kernel evaluation
+  int32_t lpw_m, lpw_z, lpw_i;  // lines per work item: length-m FFT stages, depth FFT, interp/spread
+  int32_t pow2;               // every FFT length is a power of two
+  int32_t span_max;           // bound on the range of first-tap indices of one line's nodes
+  int32_t pad1_;
   double c, K, alpha;
   double ck;                  // c*K
   // node and weight:  nu+^2 = a1 k1^2 + a2 k2^2 + b l^2 ;  W = wcoef |l| / nu+
@@ -45,6 +53,7 @@ struct Inst {
   const void* tw;        // cplx<T>[]
   const int32_t* perm;   // int32[]
   const void* sn;        // T[nt]: e^{alpha K} / I0(K sqrt(alpha^2 - theta_n^2))
+  const void* poly_c;    // T[taps][deg+1]: tap t as a polynomial in x = 2 (delta - cK) + 1
   // workspace byte offsets
   int64_t off_g, off_u, off_f;
 };

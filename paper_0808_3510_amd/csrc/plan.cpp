@@ -64,6 +64,66 @@ std::vector<int32_t> dif_positions(int L, const std::vector<int>& rad) {
   return pos;
 }
 
+// The interpolation kernel of the tap loop (see kernels.hip, kb_phi):
+// Psi_hat(u) I0(alpha K) / (2 e^{alpha K}) = e^{alpha (s - K)} (1 - e^{-2 alpha s}) / (2 s).
+double kb_phi_host(double u, double K, double a) {
+  double s2 = (K - u) * (K + u);
+  if (s2 < 0) s2 = 0;
+  const double s = std::sqrt(s2);
+  const double as = a * s;
+  const double v = as > 1e-3 ? -std::expm1(-2.0 * as) / (2.0 * s) : a * (1.0 - as + 2.0 / 3.0 * as * as);
+  return std::exp(a * (s - K)) * v;
+}
+
+// Tap t of a node with fractional offset delta in (cK - 1, cK] weighs
+// phi((delta - t)/c).  Writing delta = cK - 1/2 + x/2, x in (-1, 1], each tap
+// is a smooth function of x; it is interpolated at the D+1 Chebyshev points
+// and stored in monomial form.  Returns the largest error on a fine grid
+// relative to the largest tap value.
+double fit_tap_polys(double c, double K, double a, int taps, int D, std::vector<double>* coef) {
+  const int N = D + 1;
+  coef->assign((size_t)taps * N, 0.0);
+  double fmax = 0.0, emax = 0.0;
+  const double ck = c * K;
+  for (int t = 0; t < taps; ++t) {
+    auto f = [&](double x) { return kb_phi_host((ck - 0.5 + 0.5 * x - t) / c, K, a); };
+    std::vector<double> fx(N), ch(N, 0.0);
+    for (int k = 0; k < N; ++k) fx[k] = f(std::cos(kPi * (k + 0.5) / N));
+    for (int n = 0; n < N; ++n) {
+      double acc = 0.0;
+      for (int k = 0; k < N; ++k) acc += fx[k] * std::cos(kPi * n * (k + 0.5) / N);
+      ch[n] = (n == 0 ? 1.0 : 2.0) * acc / N;
+    }
+    // Chebyshev -> monomial: T0 = 1, T1 = x, T_{n+1} = 2 x T_n - T_{n-1}
+    std::vector<double> tp(N, 0.0), tc(N, 0.0), tn(N, 0.0), mono(N, 0.0);
+    tp[0] = 1.0;
+    if (N > 1) tc[1] = 1.0;
+    for (int i = 0; i < N; ++i) mono[i] += ch[0] * tp[i];
+    if (N > 1)
+      for (int i = 0; i < N; ++i) mono[i] += ch[1] * tc[i];
+    for (int n = 2; n < N; ++n) {
+      for (int i = 0; i < N; ++i) tn[i] = (i > 0 ? 2.0 * tc[i - 1] : 0.0) - tp[i];
+      for (int i = 0; i < N; ++i) mono[i] += ch[n] * tn[i];
+      tp = tc;
+      tc = tn;
+    }
+    for (int i = 0; i < N; ++i) (*coef)[(size_t)t * N + i] = mono[i];
+    for (int k = 0; k <= 2000; ++k) {
+      const double x = -1.0 + k / 1000.0;
+      double p = 0.0;
+      for (int i = N - 1; i >= 0; --i) p = p * x + mono[i];
+      const double v = f(x);
+      fmax = std::fmax(fmax, std::fabs(v));
+      emax = std::fmax(emax, std::fabs(p - v));
+    }
+  }
+  return fmax > 0 ? emax / fmax : 0.0;
+}
+
+bool is_pow2(int L) { return L > 0 && (L & (L - 1)) == 0; }
+
+int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 bool is_int(double v, double tol = 1e-9) { return std::fabs(v - std::nearbyint(v)) <= tol * std::fmax(1.0, std::fabs(v)); }
@@ -207,6 +267,11 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   const int lmax = n1 > n2 ? n1 : n2;
   while (tb > 1 && (size_t)lmax * tb * cs > 65536) tb /= 2;
   I.tb = tb;
+  I.pow2 = is_pow2(n1) && is_pow2(n2) && is_pow2(m) && is_pow2(g.nz);
+  I.lpw_m = clampi(2048 / m, 1, 16);
+  I.lpw_z = clampi(2048 / g.nz, 1, 16);
+  I.lpw_i = clampi(kBlock / g.nz, 1, 8);
+  while (I.lpw_i > 1 && (size_t)I.lpw_i * m * cs > 65536) --I.lpw_i;
   I.c = g.c;
   I.K = g.K;
   I.alpha = g.alpha;
@@ -217,6 +282,11 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.b = (tv / (g.nz * g.dz)) * (tv / (g.nz * g.dz));
   I.wcoef = 2.0 * g.vs * (g.dt / g.dz) * std::sqrt(I.b);
   I.scale = 1.0 / (kPi * g.c * (double)n1 * (double)n2 * (double)g.nz);
+  {
+    const double h1v = n1 / 2, h2v = n2 / 2, hz = g.nz / 2;
+    const double numax = std::sqrt(I.a1 * h1v * h1v + I.a2 * h2v * h2v + I.b * hz * hz);
+    I.span_max = (int32_t)std::ceil(2.0 * g.c * numax) + 4;
+  }
 
   // table layout
   size_t off = align256(sizeof(Inst));
@@ -238,6 +308,12 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   off = align256(off + perm_elems * sizeof(int32_t));
   const size_t off_sn = off;
   off = align256(off + (size_t)g.nt * rs);
+  const int deg = prec == PAT_F64 ? kPolyDegD : kPolyDegF;
+  std::vector<double> coef;
+  const double fit_err = fit_tap_polys(g.c, g.K, g.alpha, taps, deg, &coef);
+  I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 1e-8) ? 1 : 0;
+  const size_t off_poly = off;
+  off = align256(off + coef.size() * rs);
   const size_t total = off;
 
   p->blob.assign(total, 0);
@@ -291,6 +367,15 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
       put(p->blob, o, &f, 1);
     }
   }
+  for (size_t i = 0; i < coef.size(); ++i) {
+    const size_t o = off_poly + i * rs;
+    if (prec == PAT_F64) {
+      put(p->blob, o, &coef[i], 1);
+    } else {
+      const float f = (float)coef[i];
+      put(p->blob, o, &f, 1);
+    }
+  }
   // workspace: G (lines x nt), grid (lines x m), F (lines x nz)
   const size_t lines = (size_t)I.lines;
   I.off_g = 0;
@@ -305,6 +390,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   p->off_tw = off_tw;
   p->off_perm = off_perm;
   p->off_sn = off_sn;
+  p->off_poly = off_poly;
   p->table_bytes = total;
   return PAT_OK;
 }
@@ -314,6 +400,7 @@ void bind_table(pat_plan* p, void* table_dev) {
   p->inst.tw = base + p->off_tw;
   p->inst.perm = reinterpret_cast<const int32_t*>(base + p->off_perm);
   p->inst.sn = base + p->off_sn;
+  p->inst.poly_c = base + p->off_poly;
   std::memcpy(p->blob.data() + p->off_desc, &p->inst, sizeof(Inst));
   p->table_dev = table_dev;
 }
