@@ -81,6 +81,43 @@ def per_stage(plan, p, f, steps, torch):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
+def standalone_stages(n, g, steps, torch, dev, pat):
+    """HBM roofline of the interpolation (a3) and spreading kernels run alone
+    on full-size line sets: read grid + write node values, or the reverse."""
+    res = {}
+    for prec in ("f32", "bf16grid"):
+        plan = pat.Plan(n, n, g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], precision=prec, device=dev)
+        gen = torch.Generator(device=dev).manual_seed(7)
+        if prec == "bf16grid":
+            grid = torch.randn((plan.lines, plan.m, 2), device=dev, generator=gen).to(torch.bfloat16)
+            gbytes = 4
+        else:
+            grid = torch.randn((plan.lines, plan.m), device=dev, dtype=torch.complex64, generator=gen)
+            gbytes = 8
+        vals = torch.randn((plan.lines, plan.nz), device=dev, dtype=torch.complex64, generator=gen)
+        out = plan.nufft2_lines(grid)
+        gout = plan.nufft1_lines(vals)
+        torch.cuda.synchronize()
+        nbytes = plan.lines * plan.m * gbytes + plan.lines * plan.nz * 8
+        plan.set_timing(True)
+        plan.stage_times()
+        for _ in range(steps):
+            plan.nufft2_lines(grid, out=out)
+        t_i = [ms for name, ms in plan.stage_times()]
+        for _ in range(steps):
+            plan.nufft1_lines(vals, out=gout)
+        t_s = [ms for name, ms in plan.stage_times()]
+        plan.set_timing(False)
+        for key, ts in (("interp", t_i), ("spread", t_s)):
+            avg = sum(ts) / len(ts)
+            gbs = nbytes / (avg * 1e-3) / 1e9
+            res[f"{key}_{prec}"] = {"avg_launch_ms": avg, "algorithmic_bytes_per_launch": nbytes,
+                                    "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / PEAK_HBM_GBS,
+                                    "launches_timed": len(ts)}
+        del plan
+    return res
+
+
 def cpu_baseline(p_np, g, f_gpu, budget_s, np):
     """The oracle (as it stands) on a bounded sample: its transverse DFT in
     full, plus its direct nonuniform DFT sums on a random sample of lines,
@@ -221,7 +258,19 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
                      "launches_timed": counts[dom]},
     }
-    del plan, f
+    # adjoint R^T on the same plan (the gradient of R)
+    q = f.detach().clone()
+    pt = torch.empty_like(p_np_dev := torch.empty((n, n, nt), dtype=f.dtype, device=dev))
+    for _ in range(args.warmup):
+        plan.reconstruct_adjoint(q, out=pt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.reconstruct_adjoint(q, out=pt)
+    torch.cuda.synchronize()
+    out["adjoint_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+    del plan, f, q, pt, p_np_dev
+    out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
     if not args.no_fp64 and args.precision != "f64":
         print("[bench] timing f64", file=sys.stderr, flush=True)
         plan64, f64, ms64, st64, _ = run_prec("f64")

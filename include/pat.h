@@ -148,6 +148,25 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
  *   conventions of pat_reconstruct. */
 pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream);
 
+/* Spreading alone (type-1; the step of R^T that pat_nufft2_lines mirrors):
+ * the exact adjoint of pat_nufft2_lines for the complex inner product,
+ *   grid = N^H values  where  out = N grid  is pat_nufft2_lines,
+ * so every grid cell gathers the 2cK-tap kernel weights of the nodes whose
+ * window covers it (periodic in the grid index), times conj(W e^{-i pi nu})
+ * / (nx[0] nx[1] nz); on l = -nz/2 the value feeds both nodes -+|nu| with
+ * half weight.  values: (lines, nz) complex in the plan's element type, l in
+ * DFT order; grid: (lines, c*nt) in the plan's grid storage.  Deterministic
+ * (no atomics). */
+pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void* stream);
+
+/* Line-stage layout.  By default (fused = 1) the deconvolution, oversampled
+ * FFT, interpolation and depth DFT of each line group run in one kernel and
+ * the oversampled grid never reaches memory (likewise for the spreading
+ * side).  fused = 0 runs them as separate kernels that store the grid in the
+ * workspace.  PAT_F32_BF16GRID plans are always staged (the option concerns
+ * the stored grid): asking them for fused = 1 returns PAT_ERR_UNSUPPORTED. */
+pat_status pat_plan_set_fused(pat_plan* plan, int32_t fused);
+
 /* Per-kernel timing.  pat_plan_set_timing(plan, 1) makes later transforms of
  * this plan (and batched calls whose first plan it is) record a hipEvent
  * before and after every kernel on their stream.  pat_plan_stage_times()

@@ -206,6 +206,24 @@ pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* s
   return PAT_OK;
 }
 
+pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void* stream) {
+  pat_status s = check_plan(plan);
+  if (s != PAT_OK) return s;
+  if (!aligned16(values) || !aligned16(grid)) return set_err(PAT_ERR_INVALID_ARG, "values/grid NULL or not 16-byte aligned");
+  const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
+  hipError_t e = pat::run_spread(plan->prec, plan->inst, d, values, grid, static_cast<hipStream_t>(stream), timer_of(plan));
+  if (e != hipSuccess) return hip_err(e, "kernel launch");
+  return PAT_OK;
+}
+
+pat_status pat_plan_set_fused(pat_plan* plan, int32_t fused) {
+  if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
+  if (fused && !plan->fusable) return set_err(PAT_ERR_UNSUPPORTED, "this plan cannot run the fused line kernels");
+  // the launchers choose kernels from the host copy of the descriptor
+  plan->inst.fused = fused ? 1 : 0;
+  return PAT_OK;
+}
+
 pat_status pat_plan_set_timing(pat_plan* plan, int32_t on) {
   if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
   plan->timing = on != 0;

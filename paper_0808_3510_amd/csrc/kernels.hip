@@ -15,6 +15,10 @@
 //                 and the Jacobian weight (eq. fft-0)
 //   k_line_spread its transpose (type-1), gathered per grid cell over the
 //                 monotone node list of the line: no atomics, deterministic
+//   k_line_nufft2 a2 + a3 + inverse depth DFT fused per line group in LDS
+//   k_line_nufft1 depth DFT + spreading + transposed a2 fused per line in LDS
+// The fused kernels never store the oversampled grid; the staged ones do
+// (bf16 grid option, and the stand-alone a3 / spreading entry points).
 //
 // Uniform FFTs are in-place decimation-in-frequency mixed-radix transforms in
 // LDS; bin k ends at position perm[k] (a table built by the host plan).  Two
@@ -282,6 +286,28 @@ __device__ __forceinline__ void divmod(int e, int L, int* q, int* r) {
   }
 }
 
+
+// Issues U independent loads per thread before storing them, so that each
+// thread keeps several memory requests in flight:
+// for e in [tid, total) step kBlock:  st(e, ld(e)).
+template <int U, typename Ld, typename St>
+__device__ __forceinline__ void copy_batched(int total, Ld ld, St st) {
+  using V = decltype(ld(0));
+  for (int e0 = threadIdx.x; e0 < total; e0 += U * kBlock) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < total) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < total) st(e, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel interpolation kernel.  With s = sqrt(K^2 - u^2), |u| <= K,
 //   Psi_hat(u) I0(alpha K) / (2 e^{alpha K}) = e^{alpha (s - K)} (1 - e^{-2 alpha s}) / (2 s)
@@ -305,7 +331,7 @@ __device__ __forceinline__ T kb_phi(T u, T K, T alpha) {
   return m_exp(alpha * (s - K)) * v;
 }
 
-// tap t of a node whose offset is x = 2 (delta - cK) + 1, from the table
+// tap of a node whose offset is x = 2 (delta - cK) + 1, from its coefficient row
 template <typename T>
 __device__ __forceinline__ T tap_poly(const T* __restrict__ c, T x) {
   constexpr int D = Deg<T>::v;
@@ -338,38 +364,237 @@ __device__ __forceinline__ cx<T> phase_mpi(double nu) {
   return mk(c, -s);
 }
 
-// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m]
-template <typename T>
+// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m].  TAPS > 0 fixes the
+// tap count at compile time: the grid values are read first and the TAPS
+// polynomials advance as independent Horner chains on workgroup-uniform
+// coefficients.
+template <typename T, int TAPS>
 __device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, const Inst& I) {
   const NodePos np = node_pos(nu, I.c, I.ck);
-  int jm = np.j0 % m;
-  if (jm < 0) jm += m;
-  const int taps = I.taps;
+  int j0 = np.j0 % m;
+  if (j0 < 0) j0 += m;
   cx<T> acc = mk(T(0), T(0));
-  if (I.poly) {
+  constexpr int D = Deg<T>::v;
+  constexpr int D1 = D + 1;
+  if (TAPS > 0 && I.poly) {
+    constexpr int NT = TAPS > 0 ? TAPS : 1;
+    cx<T> g[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      int j = j0 + t;
+      if (j >= m) j -= m;
+      g[t] = U[j];
+    }
     const T x = (T)(2.0 * (np.delta - I.ck) + 1.0);
-    const T* pc = static_cast<const T*>(I.poly_c);
-    constexpr int D1 = Deg<T>::v + 1;
-    for (int t = 0; t < taps; ++t) {
-      const T w = tap_poly<T>(pc + t * D1, x);
-      const cx<T> g = U[jm];
-      acc.x += w * g.x;
-      acc.y += w * g.y;
-      ++jm;
-      if (jm == m) jm = 0;
+    const T* __restrict__ pc = static_cast<const T*>(I.poly_c);
+    T w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w[t] = pc[t * D1 + D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) w[t] = w[t] * x + pc[t * D1 + d];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc.x += w[t] * g[t].x;
+      acc.y += w[t] * g[t].y;
     }
   } else {
-    const T delta = (T)np.delta, cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
-    for (int t = 0; t < taps; ++t) {
-      const T w = kb_phi<T>((delta - T(t)) * cinv, K, alpha);
-      const cx<T> g = U[jm];
-      acc.x += w * g.x;
-      acc.y += w * g.y;
-      ++jm;
-      if (jm == m) jm = 0;
+    const int taps = I.taps;
+    int jm = j0;
+    if (I.poly) {
+      const T x = (T)(2.0 * (np.delta - I.ck) + 1.0);
+      const T* pc = static_cast<const T*>(I.poly_c);
+      for (int t = 0; t < taps; ++t) {
+        const T w = tap_poly<T>(pc + t * D1, x);
+        const cx<T> g = U[jm];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+        if (++jm == m) jm = 0;
+      }
+    } else {
+      const T delta = (T)np.delta, cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
+      for (int t = 0; t < taps; ++t) {
+        const T w = kb_phi<T>((delta - T(t)) * cinv, K, alpha);
+        const cx<T> g = U[jm];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+        if (++jm == m) jm = 0;
+      }
     }
   }
   return cmul(acc, phase_mpi<T>(nu));
+}
+
+__device__ __forceinline__ double line_ak(const Inst& I, int line) {
+  const int k1 = line / I.n2;
+  const int k2i = line - k1 * I.n2;
+  const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
+  return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
+}
+
+// a3 over a group of nl lines whose grids sit in LDS in natural order
+// (U + b*m).  mode 0 (R): node sign(l) nu+, weight wcoef |l| / nu+ (0 at
+// l = 0), mean of the nodes -+nu+ on l = -nz/2.  mode 1 (A^T): mean of the
+// nodes +-nu+ for every l, no weight.  put(e, value) receives output e = b*nz + l_index.
+template <typename T, int TAPS, typename Put>
+__device__ __forceinline__ void interp_lines(const Inst& I, const cx<T>* U, int line0, int nl, int mode, Put put) {
+  const int m = I.m, nz = I.nz;
+  for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
+    const int b = e / nz;
+    const int il = e - b * nz;
+    const cx<T>* Ub = U + b * m;
+    const double Ak = line_ak(I, line0 + b);
+    const int l = 2 * il < nz ? il : il - nz;
+    const double nup = sqrt(Ak + I.b * (double)l * (double)l);
+    cx<T> v;
+    if (mode == 0) {
+      if (l == 0) {
+        v = mk(T(0), T(0));
+      } else {
+        const double w = I.wcoef * (double)(l < 0 ? -l : l) / nup * I.scale;
+        if (2 * l == -nz) {
+          v = cadd(interp_eval<T, TAPS>(Ub, m, -nup, I), interp_eval<T, TAPS>(Ub, m, nup, I));
+          v = cscl(v, T(0.5 * w));
+        } else {
+          v = cscl(interp_eval<T, TAPS>(Ub, m, l > 0 ? nup : -nup, I), T(w));
+        }
+      }
+    } else {
+      v = cadd(interp_eval<T, TAPS>(Ub, m, nup, I), interp_eval<T, TAPS>(Ub, m, -nup, I));
+      v = cscl(v, T(0.5 * I.scale));
+    }
+    put(e, v);
+  }
+}
+
+// Type-1 spreading of one line, the transpose of interp_lines' sum.  The
+// line's nodes are listed in increasing order (monotone in l by construction)
+// with their first tap j0, polynomial offset x and value; a start table maps
+// each first-tap index v to the first node with j0 >= v, so grid cell j (and
+// each periodic image j + q m) gathers exactly the nodes with j0 in
+// (j - taps, j], in node order: no atomics, deterministic.
+//   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
+//     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
+//     whose value feeds both -nu+ and +nu+.
+//   mode 1 (A): nodes -nu+(nz/2) .. -nu+(0), +nu+(0) .. +nu+(nz/2); value
+//     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
+// Fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
+template <typename T>
+struct SpreadLds {
+  cx<T>* val;
+  T* xs;
+  T* coef;
+  int* j0s;
+  int* start;
+  static __device__ __forceinline__ SpreadLds carve(void* base, int nz, int taps) {
+    constexpr int D1 = Deg<T>::v + 1;
+    SpreadLds s;
+    const int nn = nz + 2;
+    s.val = static_cast<cx<T>*>(base);
+    s.xs = reinterpret_cast<T*>(s.val + nn);
+    s.coef = s.xs + nn;
+    s.j0s = reinterpret_cast<int*>(s.coef + taps * D1);
+    s.start = s.j0s + nn;
+    return s;
+  }
+  static size_t bytes(int nz, int taps, int span_max) {
+    constexpr int D1 = Deg<T>::v + 1;
+    return ((size_t)nz + 2) * (sizeof(cx<T>) + sizeof(T) + sizeof(int)) + (size_t)taps * D1 * sizeof(T) +
+           ((size_t)span_max + 2) * sizeof(int);
+  }
+};
+
+template <typename T, typename Fget, typename Put>
+__device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, SpreadLds<T> L, Fget fget, Put put) {
+  const int m = I.m, nz = I.nz, taps = I.taps;
+  constexpr int D1 = Deg<T>::v + 1;
+  const int nn = mode == 0 ? nz + 1 : nz + 2;
+  const double Ak = line_ak(I, line);
+  const int half = nz / 2;
+  if (I.poly) {
+    const T* pc = static_cast<const T*>(I.poly_c);
+    for (int i = threadIdx.x; i < taps * D1; i += kBlock) L.coef[i] = pc[i];
+  }
+  for (int i = threadIdx.x; i < nn; i += kBlock) {
+    double nu, cf;
+    cx<T> q;
+    if (mode == 0) {
+      const int l = i < nz ? i - half : half;
+      const double nup = sqrt(Ak + I.b * (double)l * (double)l);
+      const int lm = l < 0 ? l + nz : (l == half ? half : l);
+      q = fget(lm);
+      if (i == nz) {
+        nu = nup;
+        cf = 0.5 * I.wcoef * (double)half / nup;
+      } else {
+        nu = l > 0 ? nup : (l < 0 ? -nup : 0.0);
+        cf = l == 0 ? 0.0 : I.wcoef * (double)(l < 0 ? -l : l) / nup;
+        if (l == -half) cf *= 0.5;
+      }
+      cf *= I.scale;
+    } else {
+      int mp;
+      double sg;
+      if (i <= half) {
+        mp = half - i;
+        sg = -1.0;
+      } else {
+        mp = i - half - 1;
+        sg = 1.0;
+      }
+      const double nup = sqrt(Ak + I.b * (double)mp * (double)mp);
+      nu = sg * nup;
+      q = fget(mp);
+      if (mp != 0 && mp != half) q = cadd(q, fget(nz - mp));
+      cf = 0.5 * I.scale;
+    }
+    const NodePos np = node_pos(nu, I.c, I.ck);
+    L.val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
+    L.xs[i] = (T)(2.0 * (np.delta - I.ck) + 1.0);
+    L.j0s[i] = np.j0;
+  }
+  __syncthreads();
+  const int jlo = L.j0s[0];
+  int span = L.j0s[nn - 1] - jlo + 1;
+  span = span < I.span_max ? span : I.span_max;
+  for (int i = threadIdx.x; i < nn; i += kBlock) {
+    const int v0 = (i == 0 ? jlo : L.j0s[i - 1] + 1) - jlo;
+    const int v1 = L.j0s[i] - jlo;
+    for (int v = v0; v <= v1 && v < span; ++v) L.start[v] = i;
+  }
+  if (threadIdx.x == 0) L.start[span] = nn;
+  __syncthreads();
+  const int jhi = jlo + span - 1 + taps - 1;
+  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha), ckh = T(I.ck - 0.5);
+  for (int j = threadIdx.x; j < m; j += kBlock) {
+    cx<T> acc = mk(T(0), T(0));
+    // first periodic image j + q m that can be covered
+    int q0 = jlo - j;
+    q0 = q0 >= 0 ? (q0 + m - 1) / m : -((-q0) / m);
+    for (int jp = j + q0 * m; jp <= jhi; jp += m) {
+      int v0 = jp - taps + 1 - jlo;
+      int v1 = jp - jlo;
+      v0 = v0 > 0 ? v0 : 0;
+      v1 = v1 < span - 1 ? v1 : span - 1;
+      if (v0 > v1) continue;
+      const int i1 = L.start[v1 + 1];
+      for (int i = L.start[v0]; i < i1; ++i) {
+        const int t = jp - L.j0s[i];
+        T w;
+        if (I.poly) {
+          w = tap_poly<T>(L.coef + t * D1, L.xs[i]);
+        } else {
+          w = kb_phi<T>((ckh + T(0.5) * L.xs[i] - T(t)) * cinv, K, alpha);
+        }
+        const cx<T> vv = L.val[i];
+        acc.x += w * vv.x;
+        acc.y += w * vv.y;
+      }
+    }
+    put(j, acc);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -422,37 +647,55 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
 extern __shared__ __align__(16) unsigned char pat_smem[];
 
 // ---------------------------------------------------------------------------
-// Transverse passes.  Tiles of tb consecutive samples (t or z, the contiguous
-// axis) by the full transform length; lane -> sample, so global accesses are
-// contiguous runs of tb elements.
+// Transverse passes.  Tiles of consecutive samples (t or z, the contiguous
+// axis) by the full transform length; lanes run along the samples, so global
+// accesses are contiguous runs.  The real passes pack two neighbouring real
+// samples into one complex column (real and imaginary part) and separate the
+// two transforms afterwards, so a tile of tb complex columns covers 2 tb
+// samples.
 
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
-  const int len = a.len_nz ? I.nz : I.nt;
+  const int len = a.len_nz ? I.nz : I.nt;  // even
   const int tb = I.tb;
-  const int ntile = (len + tb - 1) / tb;
+  const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const int x2 = li / ntile;
-  const int t0 = (li - x2 * ntile) * tb;
+  const int t0 = (li - x2 * ntile) * 2 * tb;
   const T* in = static_cast<const T*>(a.in[inst_]);
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]);
   const int L = I.n1;
-  for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    int x, b;
-    divmod<true>(e, tb, &x, &b);
-    const int t = t0 + b;
-    const T v = t < len ? in[((size_t)x * I.n2 + x2) * len + t] : T(0);
-    buf[e] = mk(v, T(0));
-  }
+  const size_t rstride = (size_t)I.n2 * len;
+  const T* in0 = in + (size_t)x2 * len + t0;
+  copy_batched<8>(
+      L * tb,
+      [&](int e) {
+        int x, b;
+        divmod<true>(e, tb, &x, &b);
+        // samples t0 + 2b (real part) and t0 + 2b + 1 (imaginary part); len is even
+        return t0 + 2 * b < len ? *reinterpret_cast<const cx<T>*>(in0 + x * rstride + 2 * b) : mk(T(0), T(0));
+      },
+      [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
   fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
+  cx<T>* out0 = out + (size_t)x2 * len + t0;
   for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
     int k, b;
     divmod<true>(e, tb, &k, &b);
-    const int t = t0 + b;
-    if (t < len) out[((size_t)k * I.n2 + x2) * len + t] = buf[perm[k] * tb + b];
+    if (t0 + 2 * b >= len) continue;
+    const int kn = k == 0 ? 0 : L - k;
+    const cx<T> z = buf[perm[k] * tb + b];
+    const cx<T> zn = cconj(buf[perm[kn] * tb + b]);
+    const T h = T(0.5);
+    // transforms of the real and imaginary parts
+    const cx<T> pa = cscl(cadd(z, zn), h);
+    const cx<T> d = csub(z, zn);
+    const cx<T> pb = mk(h * d.y, -h * d.x);
+    cx<T>* o = out0 + (size_t)k * rstride + 2 * b;
+    o[0] = pa;
+    o[1] = pb;
   }
   PAT_END_ITEM
 }
@@ -466,76 +709,92 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   const int ntile = (len + tb - 1) / tb;
   const int k1 = li / ntile;
   const int t0 = (li - k1 * ntile) * tb;
-  cx<T>* io = static_cast<cx<T>*>(a.out[inst_]);
+  cx<T>* io = static_cast<cx<T>*>(a.out[inst_]) + (size_t)k1 * I.n2 * len + t0;
   const int L = I.n2;
   const bool inv = a.mode != 0;
-  for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    int x, b;
-    divmod<true>(e, tb, &x, &b);
-    const int t = t0 + b;
-    const cx<T> v = t < len ? io[((size_t)k1 * L + x) * len + t] : mk(T(0), T(0));
-    buf[e] = inv ? cconj(v) : v;
-  }
+  copy_batched<8>(
+      L * tb,
+      [&](int e) {
+        int x, b;
+        divmod<true>(e, tb, &x, &b);
+        const cx<T> v = t0 + b < len ? io[(size_t)x * len + b] : mk(T(0), T(0));
+        return inv ? cconj(v) : v;
+      },
+      [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
   fft_lds<T, P2, false>(buf, I.f2, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f2.perm;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
     int k, b;
     divmod<true>(e, tb, &k, &b);
-    const int t = t0 + b;
-    if (t < len) {
+    if (t0 + b < len) {
       const cx<T> v = buf[perm[k] * tb + b];
-      io[((size_t)k1 * L + k) * len + t] = inv ? cconj(v) : v;
+      io[(size_t)k * len + b] = inv ? cconj(v) : v;
     }
   }
   PAT_END_ITEM
 }
 
 // Inverse DFT over the first axis from bins 0..n1/2 (the others are the
-// complex conjugates of their mirror bins), keeping the real part.
+// complex conjugates of their mirror bins), real part.  Two neighbouring
+// samples are transformed together: Z = X_a + i X_b inverts to x_a + i x_b.
+// The imaginary parts of the bins 0 and n1/2 are dropped, which is what
+// taking the real part of the full inverse DFT does.
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
   const int len = a.len_nz ? I.nz : I.nt;
   const int tb = I.tb;
-  const int ntile = (len + tb - 1) / tb;
+  const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const int x2 = li / ntile;
-  const int t0 = (li - x2 * ntile) * tb;
+  const int t0 = (li - x2 * ntile) * 2 * tb;
   const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]);
   T* out = static_cast<T*>(a.out[inst_]);
   const int L = I.n1;
   const int half = L / 2;
-  for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    int k, b;
-    divmod<true>(e, tb, &k, &b);
-    const int t = t0 + b;
-    const int src = k <= half ? k : L - k;
-    const cx<T> v = t < len ? in[((size_t)src * I.n2 + x2) * len + t] : mk(T(0), T(0));
-    // inverse transform as conj(FFT(conj(.))); mirrored bins are conjugated once more
-    buf[e] = k <= half ? cconj(v) : v;
-  }
+  const size_t rstride = (size_t)I.n2 * len;
+  const cx<T>* in0 = in + (size_t)x2 * len + t0;
+  copy_batched<4>(
+      L * tb,
+      [&](int e) {
+        int k, b;
+        divmod<true>(e, tb, &k, &b);
+        const int src = k <= half ? k : L - k;
+        cx<T> xa = mk(T(0), T(0)), xb = mk(T(0), T(0));
+        if (t0 + 2 * b < len) {
+          const cx<T>* p = in0 + (size_t)src * rstride + 2 * b;
+          xa = p[0];
+          xb = p[1];
+        }
+        if (k == 0 || k == half) {
+          xa.y = T(0);
+          xb.y = T(0);
+        } else if (k > half) {
+          xa = cconj(xa);
+          xb = cconj(xb);
+        }
+        // Z = xa + i xb, stored conjugated (inverse DFT as conj(FFT(conj(.))))
+        return mk(xa.x - xb.y, -(xa.y + xb.x));
+      },
+      [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
   fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
+  T* out0 = out + (size_t)x2 * len + t0;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
     int x, b;
     divmod<true>(e, tb, &x, &b);
-    const int t = t0 + b;
-    if (t < len) out[((size_t)x * I.n2 + x2) * len + t] = buf[perm[x] * tb + b].x;
+    if (t0 + 2 * b < len) {
+      const cx<T> y = buf[perm[x] * tb + b];  // conj of x_a + i x_b
+      *reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 2 * b) = mk(y.x, -y.y);
+    }
   }
   PAT_END_ITEM
 }
 
 // ---------------------------------------------------------------------------
 // Line stages: a group of consecutive frequency lines (k1, k2) per work item.
-
-__device__ __forceinline__ double line_ak(const Inst& I, int line) {
-  const int k1 = line / I.n2;
-  const int k2i = line - k1 * I.n2;
-  const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
-  return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
-}
 
 // DFT of length nz along each line, in place.
 template <typename T, bool P2>
@@ -547,10 +806,13 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
   const int nl = min(I.lpw_z, I.lines - line0);
   cx<T>* io = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * L;
   const bool inv = a.mode != 0;
-  for (int e = threadIdx.x; e < nl * L; e += kBlock) {
-    const cx<T> v = io[e];
-    buf[e] = inv ? cconj(v) : v;
-  }
+  copy_batched<4>(
+      nl * L,
+      [&](int e) {
+        const cx<T> v = io[e];
+        return inv ? cconj(v) : v;
+      },
+      [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
   fft_lds<T, P2, true>(buf, I.fz, static_cast<const cx<T>*>(I.tw), nl, L, 1);
   const int32_t* perm = I.perm + I.fz.perm;
@@ -563,9 +825,25 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
   PAT_END_ITEM
 }
 
-// a2: u_n = G_n s_n placed at (n - nt/2) mod m, zeros elsewhere, FFT of length m.
-// The centring turns the per-tap factor exp(i pi j / c) of eq. (nufft-a) into
-// a shift, leaving only exp(-i pi nu) per node.
+// a2 loading: u_n = G_n s_n placed at (n - nt/2) mod m, zeros elsewhere.  The
+// centring turns the per-tap factor exp(i pi j / c) of eq. (nufft-a) into a
+// shift, leaving only exp(-i pi nu) per node.
+template <typename T, bool P2>
+__device__ __forceinline__ void load_deconv_pad(const Inst& I, const cx<T>* g, int nl, cx<T>* buf) {
+  const int m = I.m, nt = I.nt;
+  const T* sn = static_cast<const T*>(I.sn);
+  copy_batched<4>(
+      nl * m,
+      [&](int e) {
+        int b, j;
+        divmod<P2>(e, m, &b, &j);
+        int n = j + nt / 2;
+        if (n >= m) n -= m;
+        return n < nt ? cscl(g[(size_t)b * nt + n], sn[n]) : mk(T(0), T(0));
+      },
+      [&](int e, cx<T> v) { buf[e] = v; });
+}
+
 template <typename T, typename G, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
@@ -573,19 +851,11 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
-  const cx<T>* g = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt;
-  G* grid = static_cast<G*>(a.out[inst_]);
-  const T* sn = static_cast<const T*>(I.sn);
-  for (int e = threadIdx.x; e < nl * m; e += kBlock) {
-    int b, j;
-    divmod<P2>(e, m, &b, &j);
-    int n = j + nt / 2;
-    if (n >= m) n -= m;
-    buf[e] = n < nt ? cscl(g[(size_t)b * nt + n], sn[n]) : mk(T(0), T(0));
-  }
+  load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, buf);
   __syncthreads();
   fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
+  G* grid = static_cast<G*>(a.out[inst_]);
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
     int b, j;
     divmod<P2>(e, m, &b, &j);
@@ -594,19 +864,12 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   PAT_END_ITEM
 }
 
-// transpose of a2: X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
-template <typename T, typename G, bool P2>
-__global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
-  PAT_FOR_EACH_ITEM(a)
+// transpose of a2 on LDS grids (natural order, conjugated on entry by the
+// caller): X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
+template <typename T, bool P2>
+__device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int nl, cx<T>* x) {
   const int m = I.m, nt = I.nt;
-  const int line0 = li * I.lpw_m;
-  const int nl = min(I.lpw_m, I.lines - line0);
-  const G* grid = static_cast<const G*>(a.in[inst_]);
-  cx<T>* x = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt;
   const T* sn = static_cast<const T*>(I.sn);
-  for (int e = threadIdx.x; e < nl * m; e += kBlock) buf[e] = cconj(GridIO<T, G>::ld(grid, (size_t)line0 * m + e));
-  __syncthreads();
   fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
   for (int e = threadIdx.x; e < nl * nt; e += kBlock) {
@@ -616,13 +879,26 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
     if (pos < 0) pos += m;
     x[e] = cscl(cconj(buf[b * m + perm[pos]]), sn[n]);
   }
+}
+
+template <typename T, typename G, bool P2>
+__global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
+  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
+  PAT_FOR_EACH_ITEM(a)
+  const int m = I.m, nt = I.nt;
+  const int line0 = li * I.lpw_m;
+  const int nl = min(I.lpw_m, I.lines - line0);
+  const G* grid = static_cast<const G*>(a.in[inst_]);
+  copy_batched<4>(
+      nl * m, [&](int e) { return cconj(GridIO<T, G>::ld(grid, (size_t)line0 * m + e)); },
+      [&](int e, cx<T> v) { buf[e] = v; });
+  __syncthreads();
+  ifft_pick_deconv<T, P2>(I, buf, nl, static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt);
   PAT_END_ITEM
 }
 
-// a3: type-2 interpolation.  mode 0 (R): node sign(l) nu+, weight
-// wcoef |l| / nu+ (0 at l = 0), mean of the nodes -+nu+ on l = -nz/2.
-// mode 1 (A^T): mean of the nodes +-nu+ for every l, no weight.
-template <typename T, typename G>
+// a3 alone: grid lines from memory, weighted node values to memory.
+template <typename T, typename G, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
@@ -630,146 +906,84 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   const int line0 = li * I.lpw_i;
   const int nl = min(I.lpw_i, I.lines - line0);
   const G* grid = static_cast<const G*>(a.in[inst_]);
-  cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
-  for (int e = threadIdx.x; e < nl * m; e += kBlock) buf[e] = GridIO<T, G>::ld(grid, (size_t)line0 * m + e);
+  copy_batched<4>(
+      nl * m, [&](int e) { return GridIO<T, G>::ld(grid, (size_t)line0 * m + e); },
+      [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
+  cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
+  interp_lines<T, TAPS>(I, buf, line0, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
+  PAT_END_ITEM
+}
+
+// spreading alone: depth spectra from memory, grid lines to memory.
+template <typename T, typename G>
+__global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
+  PAT_FOR_EACH_ITEM(a)
+  const SpreadLds<T> L = SpreadLds<T>::carve(pat_smem, I.nz, I.taps);
+  const cx<T>* F = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * I.nz;
+  G* grid = static_cast<G*>(a.out[inst_]);
+  const size_t row = (size_t)li * I.m;
+  spread_line<T>(
+      I, li, a.mode, L, [&](int l) { return F[l]; }, [&](int j, cx<T> v) { GridIO<T, G>::st(grid, row + j, v); });
+  PAT_END_ITEM
+}
+
+// Fused a2 + a3 + inverse depth DFT (operators R and A^T): per group of nl
+// lines, the detector spectrum is deconvolved, padded and transformed in
+// LDS, brought to natural order, interpolated at the line's nodes, and the
+// node values are inverse-transformed over depth before the only store.
+template <typename T, bool P2, int TAPS>
+__global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
+  PAT_FOR_EACH_ITEM(a)
+  const int m = I.m, nt = I.nt, nz = I.nz;
+  const int lpw = I.lpw_f;
+  const int line0 = li * lpw;
+  const int nl = min(lpw, I.lines - line0);
+  const int sp = m > nz ? m : nz;
+  cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
+  cx<T>* gn = gp + lpw * sp;                         // grid in natural order
+  load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, gp);
+  __syncthreads();
+  fft_lds<T, P2, true>(gp, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
+  const int32_t* permm = I.perm + I.fm.perm;
+  for (int e = threadIdx.x; e < nl * m; e += kBlock) {
+    int b, j;
+    divmod<P2>(e, m, &b, &j);
+    gn[e] = gp[b * m + permm[j]];
+  }
+  __syncthreads();
+  cx<T>* fz = gp;  // the permuted grid is no longer needed
+  interp_lines<T, TAPS>(I, gn, line0, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
+  __syncthreads();
+  fft_lds<T, P2, true>(fz, I.fz, static_cast<const cx<T>*>(I.tw), nl, nz, 1);
+  const int32_t* permz = I.perm + I.fz.perm;
+  cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
-    const int b = e / nz;
-    const int il = e - b * nz;
-    const cx<T>* U = buf + b * m;
-    const double Ak = line_ak(I, line0 + b);
-    const int l = 2 * il < nz ? il : il - nz;
-    const double nup = sqrt(Ak + I.b * (double)l * (double)l);
-    cx<T> v;
-    if (a.mode == 0) {
-      if (l == 0) {
-        v = mk(T(0), T(0));
-      } else {
-        const double w = I.wcoef * (double)(l < 0 ? -l : l) / nup * I.scale;
-        if (2 * l == -nz) {
-          v = cadd(interp_eval<T>(U, m, -nup, I), interp_eval<T>(U, m, nup, I));
-          v = cscl(v, T(0.5 * w));
-        } else {
-          v = cscl(interp_eval<T>(U, m, l > 0 ? nup : -nup, I), T(w));
-        }
-      }
-    } else {
-      v = cadd(interp_eval<T>(U, m, nup, I), interp_eval<T>(U, m, -nup, I));
-      v = cscl(v, T(0.5 * I.scale));
-    }
-    out[e] = v;
+    int b, j;
+    divmod<P2>(e, nz, &b, &j);
+    out[e] = cconj(fz[b * nz + permz[j]]);
   }
   PAT_END_ITEM
 }
 
-// a6: type-1 spreading, the transpose of k_line_interp's sum.  The line's
-// nodes are listed in increasing order (they are monotone in l by
-// construction) with their first tap j0, polynomial offset x and value.  A
-// start table maps every first-tap index v to the first node with j0 >= v, so
-// grid cell j (and each of its periodic images j + q m) gathers exactly the
-// nodes with j0 in (j - taps, j], in node order: no atomics, deterministic.
-//   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
-//     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
-//     whose value feeds both -nu+ and +nu+.
-//   mode 1 (A): nodes -nu+(nz/2) .. -nu+(0), +nu+(0) .. +nu+(nz/2); value
-//     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
-template <typename T, typename G>
-__global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
+// Fused depth DFT + spreading + transposed a2 (operators R^T and A): one line
+// per work item; only the depth line is loaded and only the time line stored.
+template <typename T, bool P2>
+__global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   PAT_FOR_EACH_ITEM(a)
-  const int m = I.m, nz = I.nz, taps = I.taps;
-  constexpr int D1 = Deg<T>::v + 1;
-  const int nn = a.mode == 0 ? nz + 1 : nz + 2;
-  cx<T>* val = reinterpret_cast<cx<T>*>(pat_smem);
-  T* xs = reinterpret_cast<T*>(val + nn);
-  T* coef = xs + nn;
-  int* j0s = reinterpret_cast<int*>(coef + taps * D1);
-  int* start = j0s + nn;
-  const cx<T>* F = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
-  G* grid = static_cast<G*>(a.out[inst_]);
-  const double Ak = line_ak(I, li);
-  const int half = nz / 2;
-  if (I.poly) {
-    const T* pc = static_cast<const T*>(I.poly_c);
-    for (int i = threadIdx.x; i < taps * D1; i += kBlock) coef[i] = pc[i];
-  }
-  for (int i = threadIdx.x; i < nn; i += kBlock) {
-    double nu, cf;
-    cx<T> q;
-    if (a.mode == 0) {
-      const int l = i < nz ? i - half : half;
-      const double nup = sqrt(Ak + I.b * (double)l * (double)l);
-      const int lm = l < 0 ? l + nz : (l == half ? half : l);
-      q = F[lm];
-      if (i == nz) {
-        nu = nup;
-        cf = 0.5 * I.wcoef * (double)half / nup;
-      } else {
-        nu = l > 0 ? nup : (l < 0 ? -nup : 0.0);
-        cf = l == 0 ? 0.0 : I.wcoef * (double)(l < 0 ? -l : l) / nup;
-        if (l == -half) cf *= 0.5;
-      }
-      cf *= I.scale;
-    } else {
-      int mp;
-      double sg;
-      if (i <= half) {
-        mp = half - i;
-        sg = -1.0;
-      } else {
-        mp = i - half - 1;
-        sg = 1.0;
-      }
-      const double nup = sqrt(Ak + I.b * (double)mp * (double)mp);
-      nu = sg * nup;
-      q = F[mp];
-      if (mp != 0 && mp != half) q = cadd(q, F[nz - mp]);
-      cf = 0.5 * I.scale;
-    }
-    const NodePos np = node_pos(nu, I.c, I.ck);
-    val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
-    xs[i] = (T)(2.0 * (np.delta - I.ck) + 1.0);
-    j0s[i] = np.j0;
-  }
+  const int m = I.m, nz = I.nz, nt = I.nt;
+  cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // m
+  cx<T>* q = grid + m;                                // nz
+  const SpreadLds<T> L = SpreadLds<T>::carve(q + nz, nz, I.taps);
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
+  copy_batched<2>(nz, [&](int e) { return in[e]; }, [&](int e, cx<T> v) { q[e] = v; });
   __syncthreads();
-  const int jlo = j0s[0];
-  int span = j0s[nn - 1] - jlo + 1;
-  span = span < I.span_max ? span : I.span_max;
-  for (int i = threadIdx.x; i < nn; i += kBlock) {
-    const int v0 = (i == 0 ? jlo : j0s[i - 1] + 1) - jlo;
-    const int v1 = j0s[i] - jlo;
-    for (int v = v0; v <= v1 && v < span; ++v) start[v] = i;
-  }
-  if (threadIdx.x == 0) start[span] = nn;
+  fft_lds<T, P2, true>(q, I.fz, static_cast<const cx<T>*>(I.tw), 1, nz, 1);
+  const int32_t* permz = I.perm + I.fz.perm;
+  spread_line<T>(
+      I, li, a.mode, L, [&](int l) { return q[permz[l]]; }, [&](int j, cx<T> v) { grid[j] = cconj(v); });
   __syncthreads();
-  const int jhi = jlo + span - 1 + taps - 1;
-  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha), ckh = T(I.ck - 0.5);
-  for (int j = threadIdx.x; j < m; j += kBlock) {
-    cx<T> acc = mk(T(0), T(0));
-    // first periodic image j + q m that can be covered
-    int q0 = jlo - j;
-    q0 = q0 >= 0 ? (q0 + m - 1) / m : -((-q0) / m);
-    for (int jp = j + q0 * m; jp <= jhi; jp += m) {
-      int v0 = jp - taps + 1 - jlo;
-      int v1 = jp - jlo;
-      v0 = v0 > 0 ? v0 : 0;
-      v1 = v1 < span - 1 ? v1 : span - 1;
-      if (v0 > v1) continue;
-      const int i1 = start[v1 + 1];
-      for (int i = start[v0]; i < i1; ++i) {
-        const int t = jp - j0s[i];
-        T w;
-        if (I.poly) {
-          w = tap_poly<T>(coef + t * D1, xs[i]);
-        } else {
-          w = kb_phi<T>((ckh + T(0.5) * xs[i] - T(t)) * cinv, K, alpha);
-        }
-        const cx<T> vv = val[i];
-        acc.x += w * vv.x;
-        acc.y += w * vv.y;
-      }
-    }
-    GridIO<T, G>::st(grid, (size_t)li * m + j, acc);
-  }
+  ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt);
   PAT_END_ITEM
 }
 
@@ -816,26 +1030,26 @@ hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStr
   return e;
 }
 
-enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LINE };
+enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LINE };
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 int items_of(const Inst& I, Items kind, bool nz) {
   const int len = nz ? I.nz : I.nt;
-  const int ntile = cdiv(len, I.tb);
   switch (kind) {
-    case IT_X1: return I.n2 * ntile;
-    case IT_X2: return I.n2 > 1 ? I.h1 * ntile : 0;
-    case IT_C2R: return I.n2 * ntile;
+    case IT_X1: return I.n2 * cdiv(len, 2 * I.tb);
+    case IT_X2: return I.n2 > 1 ? I.h1 * cdiv(len, I.tb) : 0;
+    case IT_C2R: return I.n2 * cdiv(len, 2 * I.tb);
     case IT_LM: return cdiv(I.lines, I.lpw_m);
     case IT_LZ: return cdiv(I.lines, I.lpw_z);
     case IT_LI: return cdiv(I.lines, I.lpw_i);
+    case IT_LF: return cdiv(I.lines, I.lpw_f);
     case IT_LINE: return I.lines;
   }
   return 0;
 }
 
-template <typename T, typename G, bool P2>
+template <typename T, typename G, bool P2, int TAPS>
 struct Runner {
   int n;
   const Inst* h;
@@ -846,7 +1060,6 @@ struct Runner {
   StageTimer* tm;
 
   static constexpr size_t cs = sizeof(cx<T>);
-  static constexpr int D1 = Deg<T>::v + 1;
 
   StageArgs base(Items kind, bool nz, int mode, const void* const* in, void* const* out) {
     StageArgs a;
@@ -907,15 +1120,25 @@ struct Runner {
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LI, true, mode, in, out);
-    return launch(k_line_interp<T, G>, "interp", a,
+    return launch(k_line_interp<T, G, TAPS>, "interp", a,
                   max_over([](const Inst& I) { return (size_t)I.lpw_i * I.m * cs; }), st, tm);
   }
   hipError_t spread(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LINE, true, mode, in, out);
-    return launch(k_line_spread<T, G>, "spread", a, max_over([](const Inst& I) {
-                    const size_t nn = (size_t)I.nz + 2;
-                    return nn * (cs + sizeof(T) + sizeof(int)) + (size_t)I.taps * D1 * sizeof(T) +
-                           ((size_t)I.span_max + 2) * sizeof(int) + 64;
+    return launch(k_line_spread<T, G>, "spread", a,
+                  max_over([](const Inst& I) { return SpreadLds<T>::bytes(I.nz, I.taps, I.span_max) + 64; }), st,
+                  tm);
+  }
+  hipError_t nufft2(const void* const* in, void* const* out, int mode) {
+    StageArgs a = base(IT_LF, true, mode, in, out);
+    return launch(k_line_nufft2<T, P2, TAPS>, "nufft_fused", a,
+                  max_over([](const Inst& I) { return (size_t)I.lpw_f * (I.m + (I.m > I.nz ? I.m : I.nz)) * cs; }),
+                  st, tm);
+  }
+  hipError_t nufft1(const void* const* in, void* const* out, int mode) {
+    StageArgs a = base(IT_LINE, true, mode, in, out);
+    return launch(k_line_nufft1<T, P2>, "nufft_adjoint_fused", a, max_over([](const Inst& I) {
+                    return ((size_t)I.m + I.nz) * cs + SpreadLds<T>::bytes(I.nz, I.taps, I.span_max) + 64;
                   }),
                   st, tm);
   }
@@ -927,18 +1150,20 @@ struct Runner {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
-template <typename T, typename G, bool P2>
+template <typename T, typename G, bool P2, int TAPS>
 hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
                     void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  Runner<T, G, P2> r{n, h, d, counters, 0, st, tm};
+  Runner<T, G, P2, TAPS> r{n, h, d, counters, 0, st, tm};
   void* bg[kMaxBatch];
   void* bu[kMaxBatch];
   void* bf[kMaxBatch];
+  bool fused = true;
   for (int i = 0; i < n; ++i) {
     char* w = static_cast<char*>(ws[i]);
     bg[i] = w + h[i].off_g;
     bu[i] = w + h[i].off_u;
     bf[i] = w + h[i].off_f;
+    fused = fused && h[i].fused;
   }
   if (counters) {
     if (tm) tm->begin("zero_counters", st);
@@ -951,9 +1176,13 @@ hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const voi
     case OP_AT:
       PAT_TRY(r.x1(in, bg, false));
       PAT_TRY(r.x2(bg, false, 0));
-      PAT_TRY(r.a2(bg, bu));
-      PAT_TRY(r.interp(bu, bf, op == OP_R ? 0 : 1));
-      PAT_TRY(r.zfft(bf, 1));
+      if (fused) {
+        PAT_TRY(r.nufft2(bg, bf, op == OP_R ? 0 : 1));
+      } else {
+        PAT_TRY(r.a2(bg, bu));
+        PAT_TRY(r.interp(bu, bf, op == OP_R ? 0 : 1));
+        PAT_TRY(r.zfft(bf, 1));
+      }
       PAT_TRY(r.x2(bf, true, 1));
       PAT_TRY(r.c2r(bf, out, true));
       break;
@@ -961,9 +1190,13 @@ hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const voi
     case OP_A:
       PAT_TRY(r.x1(in, bf, true));
       PAT_TRY(r.x2(bf, true, 0));
-      PAT_TRY(r.zfft(bf, 0));
-      PAT_TRY(r.spread(bf, bu, op == OP_RT ? 0 : 1));
-      PAT_TRY(r.a2t(bu, bg));
+      if (fused) {
+        PAT_TRY(r.nufft1(bf, bg, op == OP_RT ? 0 : 1));
+      } else {
+        PAT_TRY(r.zfft(bf, 0));
+        PAT_TRY(r.spread(bf, bu, op == OP_RT ? 0 : 1));
+        PAT_TRY(r.a2t(bu, bg));
+      }
       PAT_TRY(r.x2(bg, false, 1));
       PAT_TRY(r.c2r(bg, out, false));
       break;
@@ -977,11 +1210,45 @@ bool all_pow2(int n, const Inst* h) {
   return true;
 }
 
+bool all_taps(int n, const Inst* h, int taps) {
+  for (int i = 0; i < n; ++i)
+    if (h[i].taps != taps) return false;
+  return true;
+}
+
 template <typename T, typename G>
 hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
                     void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  if (all_pow2(n, h)) return run_op_t<T, G, true>(op, n, h, d, in, out, ws, counters, st, tm);
-  return run_op_t<T, G, false>(op, n, h, d, in, out, ws, counters, st, tm);
+  const bool t12 = all_taps(n, h, 12);
+  if (all_pow2(n, h)) {
+    if (t12) return run_op_t<T, G, true, 12>(op, n, h, d, in, out, ws, counters, st, tm);
+    return run_op_t<T, G, true, 0>(op, n, h, d, in, out, ws, counters, st, tm);
+  }
+  if (t12) return run_op_t<T, G, false, 12>(op, n, h, d, in, out, ws, counters, st, tm);
+  return run_op_t<T, G, false, 0>(op, n, h, d, in, out, ws, counters, st, tm);
+}
+
+template <typename T, typename G>
+hipError_t interp_only(const Inst& h, const Inst* dinst, const void* grid, void* out, hipStream_t st, StageTimer* tm) {
+  const Inst* d[1] = {dinst};
+  const void* in[1] = {grid};
+  void* o[1] = {out};
+  if (h.taps == 12) {
+    Runner<T, G, false, 12> r{1, &h, d, nullptr, 0, st, tm};
+    return r.interp(in, o, 0);
+  }
+  Runner<T, G, false, 0> r{1, &h, d, nullptr, 0, st, tm};
+  return r.interp(in, o, 0);
+}
+
+template <typename T, typename G>
+hipError_t spread_only(const Inst& h, const Inst* dinst, const void* vals, void* grid, hipStream_t st,
+                       StageTimer* tm) {
+  const Inst* d[1] = {dinst};
+  const void* in[1] = {vals};
+  void* o[1] = {grid};
+  Runner<T, G, false, 0> r{1, &h, d, nullptr, 0, st, tm};
+  return r.spread(in, o, 0);
 }
 
 }  // namespace
@@ -1001,22 +1268,20 @@ hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* 
 
 hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* grid, void* out, hipStream_t stream,
                       StageTimer* timer) {
-  const Inst* d[1] = {dinst};
-  const void* in[1] = {grid};
-  void* o[1] = {out};
   switch (prec) {
-    case PREC_F64: {
-      Runner<double, cx<double>, false> r{1, &hinst, d, nullptr, 0, stream, timer};
-      return r.interp(in, o, 0);
-    }
-    case PREC_F32: {
-      Runner<float, cx<float>, false> r{1, &hinst, d, nullptr, 0, stream, timer};
-      return r.interp(in, o, 0);
-    }
-    case PREC_BF16: {
-      Runner<float, bf2, false> r{1, &hinst, d, nullptr, 0, stream, timer};
-      return r.interp(in, o, 0);
-    }
+    case PREC_F64: return interp_only<double, cx<double>>(hinst, dinst, grid, out, stream, timer);
+    case PREC_F32: return interp_only<float, cx<float>>(hinst, dinst, grid, out, stream, timer);
+    case PREC_BF16: return interp_only<float, bf2>(hinst, dinst, grid, out, stream, timer);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* vals, void* grid, hipStream_t stream,
+                      StageTimer* timer) {
+  switch (prec) {
+    case PREC_F64: return spread_only<double, cx<double>>(hinst, dinst, vals, grid, stream, timer);
+    case PREC_F32: return spread_only<float, cx<float>>(hinst, dinst, vals, grid, stream, timer);
+    case PREC_BF16: return spread_only<float, bf2>(hinst, dinst, vals, grid, stream, timer);
   }
   return hipErrorInvalidValue;
 }

@@ -29,4 +29,9 @@ hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* 
 hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* grid, void* out,
                       hipStream_t stream, StageTimer* timer);
 
+// Spreading alone (operator R^T's type-1 step) on user buffers: depth
+// spectra in, oversampled grid lines out.
+hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* vals, void* grid,
+                      hipStream_t stream, StageTimer* timer);
+
 }  // namespace pat

@@ -39,7 +39,8 @@ struct Inst {
   int32_t lpw_m, lpw_z, lpw_i;  // lines per work item: length-m FFT stages, depth FFT, interp/spread
   int32_t pow2;               // every FFT length is a power of two
   int32_t span_max;           // bound on the range of first-tap indices of one line's nodes
-  int32_t pad1_;
+  int32_t lpw_f;              // lines per work item of the fused line kernels
+  int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
   double c, K, alpha;
   double ck;                  // c*K
   // node and weight:  nu+^2 = a1 k1^2 + a2 k2^2 + b l^2 ;  W = wcoef |l| / nu+

@@ -230,7 +230,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   const int prec = g.precision;
   const size_t cs = complex_bytes(prec);
   const size_t rs = cs / 2;
-  if ((size_t)m * cs > 131072) {
+  if (2 * (size_t)m * cs > 131072) {
     msg << "c*nt = " << m << " exceeds the LDS line capacity for this precision";
     return fail(PAT_ERR_UNSUPPORTED);
   }
@@ -263,7 +263,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.h1 = n1 / 2 + 1;
   I.lines = I.h1 * n2;
   I.taps = taps;
-  int tb = 32;
+  int tb = prec == PAT_F64 ? 16 : 32;
   const int lmax = n1 > n2 ? n1 : n2;
   while (tb > 1 && (size_t)lmax * tb * cs > 65536) tb /= 2;
   I.tb = tb;
@@ -272,6 +272,9 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.lpw_z = clampi(2048 / g.nz, 1, 16);
   I.lpw_i = clampi(kBlock / g.nz, 1, 8);
   while (I.lpw_i > 1 && (size_t)I.lpw_i * m * cs > 65536) --I.lpw_i;
+  I.lpw_f = clampi(2048 / m, 1, 16);
+  const size_t fused_row = ((size_t)m + (size_t)(m > g.nz ? m : g.nz)) * cs;
+  while (I.lpw_f > 1 && (size_t)I.lpw_f * fused_row > 65536) --I.lpw_f;
   I.c = g.c;
   I.K = g.K;
   I.alpha = g.alpha;
@@ -312,6 +315,14 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   std::vector<double> coef;
   const double fit_err = fit_tap_polys(g.c, g.K, g.alpha, taps, deg, &coef);
   I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 1e-8) ? 1 : 0;
+  {
+    // LDS of the fused adjoint line kernel: depth spectrum, node lists,
+    // tap polynomials, start table and one grid line
+    const size_t lds_spread = (size_t)g.nz * cs + ((size_t)g.nz + 2) * (cs + rs + 4) +
+                              (size_t)taps * (deg + 1) * rs + ((size_t)I.span_max + 2) * 4 + (size_t)m * cs + 64;
+    // the bf16 option stores the oversampled grid, so it runs the staged kernels
+    I.fused = (prec != PAT_F32_BF16GRID && lds_spread <= 65536 && fused_row <= 131072) ? 1 : 0;
+  }
   const size_t off_poly = off;
   off = align256(off + coef.size() * rs);
   const size_t total = off;
@@ -385,6 +396,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
 
   p->g = g;
   p->prec = prec;
+  p->fusable = I.fused != 0;
   p->inst = I;
   p->off_desc = 0;
   p->off_tw = off_tw;

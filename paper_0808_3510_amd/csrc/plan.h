@@ -17,6 +17,7 @@ struct pat_plan {
   size_t table_bytes = 0, ws_bytes = 0;
   void* table_dev = nullptr;
   bool uploaded = false;
+  bool fusable = false;    // the fused line kernels fit this geometry and precision
   bool timing = false;
   void* timer = nullptr;   // owned by the ABI layer
 };

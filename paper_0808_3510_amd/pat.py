@@ -61,6 +61,8 @@ def lib():
             "pat_reconstruct_batched": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p),
                                                   POINTER(c_void_p), vp, vp]),
             "pat_nufft2_lines": (c_int32, [vp, vp, vp, vp]),
+            "pat_nufft1_lines": (c_int32, [vp, vp, vp, vp]),
+            "pat_plan_set_fused": (c_int32, [vp, c_int32]),
             "pat_plan_set_timing": (c_int32, [vp, c_int32]),
             "pat_plan_stage_times": (c_int32, [vp, c_int32, POINTER(c_char_p), POINTER(c_float),
                                                POINTER(c_int32)]),
@@ -140,6 +142,14 @@ def pat_reconstruct_batched(plans, ps, fs, ws, stream):
 
 def pat_nufft2_lines(plan, grid, out, stream):
     _check(lib().pat_nufft2_lines(plan, grid, out, stream))
+
+
+def pat_nufft1_lines(plan, values, grid, stream):
+    _check(lib().pat_nufft1_lines(plan, values, grid, stream))
+
+
+def pat_plan_set_fused(plan, fused: bool):
+    _check(lib().pat_plan_set_fused(plan, 1 if fused else 0))
 
 
 def pat_plan_set_timing(plan, on: bool):
@@ -269,6 +279,25 @@ class Plan:
             out = torch.empty((self.lines, self.nz), dtype=cdt, device=self.device)
         pat_nufft2_lines(self.ptr, grid.data_ptr(), out.data_ptr(), _stream(self.device))
         return out
+
+    def nufft1_lines(self, values: torch.Tensor, out=None) -> torch.Tensor:
+        """Spreading alone, the adjoint of :meth:`nufft2_lines`: values
+        ``(lines, nz)`` complex -> grid ``(lines, m)`` complex (``(lines, m, 2)``
+        bfloat16 for the bf16 grid)."""
+        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+        if values.dtype != cdt or tuple(values.shape) != (self.lines, self.nz) or not values.is_contiguous():
+            raise ValueError("values have the wrong dtype, shape or layout")
+        if out is None:
+            if self.precision == "bf16grid":
+                out = torch.empty((self.lines, self.m, 2), dtype=torch.bfloat16, device=self.device)
+            else:
+                out = torch.empty((self.lines, self.m), dtype=cdt, device=self.device)
+        pat_nufft1_lines(self.ptr, values.data_ptr(), out.data_ptr(), _stream(self.device))
+        return out
+
+    def set_fused(self, fused: bool = True):
+        """Fused (default) or staged line kernels; see ``pat_plan_set_fused``."""
+        pat_plan_set_fused(self.ptr, fused)
 
     def set_timing(self, on: bool = True):
         pat_plan_set_timing(self.ptr, on)

@@ -100,3 +100,62 @@ def test_spread_is_deterministic():
     a = plan.reconstruct_adjoint(q).clone()
     b = plan.reconstruct_adjoint(q).clone()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("op", ["reconstruct", "reconstruct_adjoint", "forward", "forward_adjoint"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("gi", [1, 3])
+def test_staged_kernels_match_oracle(op, prec, gi):
+    """The staged line kernels (grid stored between stages) against the oracle."""
+    g = SMALL[gi]
+    say(f"staged {op} {prec} {g}")
+    n_in = g["nt"] if op in ("reconstruct", "forward_adjoint") else g["nz"]
+    x = inputs.random_array((g["n1"], g["n2"], n_in), 300 + gi)
+    expect = getattr(recon, op)(x, g)
+    plan = make_plan(g, prec)
+    plan.set_fused(False)
+    y = getattr(plan, op)(to_dev(x, prec))
+    torch.cuda.synchronize()
+    assert relerr(y.cpu().double().numpy(), expect) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_and_staged_agree(prec):
+    g = SMALL[0]
+    say(f"fused vs staged {prec}")
+    plan = make_plan(g, prec)
+    p = to_dev(inputs.random_array((g["n1"], g["n2"], g["nt"]), 7), prec)
+    a = plan.reconstruct(p).clone()
+    plan.set_fused(False)
+    b = plan.reconstruct(p).clone()
+    tol = 1e-6 if prec == "f32" else 1e-13
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() < tol
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16grid"])
+def test_spread_lines_is_adjoint_of_interp_lines(prec):
+    """<N U, V> = <U, N^H V> for the stand-alone stages (same kernel weights
+    on both sides, so exact up to rounding)."""
+    g = SMALL[1]
+    say(f"nufft1 adjoint {prec}")
+    plan = make_plan(g, prec)
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    rg = inputs.rng(8)
+    U = rg.standard_normal((plan.lines, plan.m)) + 1j * rg.standard_normal((plan.lines, plan.m))
+    V = rg.standard_normal((plan.lines, plan.nz)) + 1j * rg.standard_normal((plan.lines, plan.nz))
+    Vd = torch.from_numpy(V).to(DEV, cdt)
+    NhV = plan.nufft1_lines(Vd)
+    if prec == "bf16grid":
+        Ub = torch.from_numpy(np.stack([U.real, U.imag], -1)).to(DEV, torch.bfloat16).contiguous()
+        Uc = Ub.float()
+        Uc = torch.complex(Uc[..., 0], Uc[..., 1]).to(cdt)
+        NU = plan.nufft2_lines(Ub)
+        NhV = torch.complex(NhV.float()[..., 0], NhV.float()[..., 1])
+        tol = 1e-2
+    else:
+        Uc = torch.from_numpy(U).to(DEV, cdt)
+        NU = plan.nufft2_lines(Uc)
+        tol = 1e-5 if prec == "f32" else 1e-12
+    a = torch.vdot(Vd.flatten(), NU.flatten()).item()   # <V, N U>
+    b = torch.vdot(NhV.flatten().to(cdt), Uc.flatten()).item()  # <N^H V, U>
+    assert abs(a - b) <= tol * abs(a)
