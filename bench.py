@@ -260,7 +260,7 @@ def main():
     }
     # adjoint R^T on the same plan (the gradient of R)
     q = f.detach().clone()
-    pt = torch.empty_like(p_np_dev := torch.empty((n, n, nt), dtype=f.dtype, device=dev))
+    pt = torch.empty((n, n, nt), dtype=f.dtype, device=dev)
     for _ in range(args.warmup):
         plan.reconstruct_adjoint(q, out=pt)
     torch.cuda.synchronize()
@@ -269,7 +269,7 @@ def main():
         plan.reconstruct_adjoint(q, out=pt)
     torch.cuda.synchronize()
     out["adjoint_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
-    del plan, f, q, pt, p_np_dev
+    del plan, f, q, pt
     out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
     if not args.no_fp64 and args.precision != "f64":
         print("[bench] timing f64", file=sys.stderr, flush=True)

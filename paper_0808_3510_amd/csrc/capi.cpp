@@ -87,7 +87,8 @@ pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, 
   const void* ins[1] = {in};
   void* outs[1] = {out};
   void* wss[1] = {ws};
-  hipError_t e = pat::run_op(plan->prec, op, 1, &plan->inst, dd, ins, outs, wss, nullptr,
+  const void* hp[1] = {plan->blob.data() + plan->off_poly};
+  hipError_t e = pat::run_op(plan->prec, op, 1, &plan->inst, dd, hp, ins, outs, wss, nullptr,
                              static_cast<hipStream_t>(stream), timer_of(plan));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
@@ -175,6 +176,7 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
   if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
   pat::Inst h[pat::kMaxBatch];
   const pat::Inst* d[pat::kMaxBatch];
+  const void* hp[pat::kMaxBatch];
   void* wsi[pat::kMaxBatch];
   unsigned char* w = static_cast<unsigned char*>(ws);
   uint32_t* counters = reinterpret_cast<uint32_t*>(w);
@@ -186,11 +188,12 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
     if (!aligned16(p[i]) || !aligned16(f[i]))
       return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
     h[i] = plans[i]->inst;
+    hp[i] = plans[i]->blob.data() + plans[i]->off_poly;
     d[i] = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plans[i]->table_dev) + plans[i]->off_desc);
     wsi[i] = w + off;
     off += align256(plans[i]->ws_bytes);
   }
-  hipError_t e = pat::run_op(plans[0]->prec, pat::OP_R, n, h, d, p, f, wsi, counters,
+  hipError_t e = pat::run_op(plans[0]->prec, pat::OP_R, n, h, d, hp, p, f, wsi, counters,
                              static_cast<hipStream_t>(stream), timer_of(plans[0]));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
@@ -201,7 +204,8 @@ pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* s
   if (s != PAT_OK) return s;
   if (!aligned16(grid) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "grid/out NULL or not 16-byte aligned");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
-  hipError_t e = pat::run_interp(plan->prec, plan->inst, d, grid, out, static_cast<hipStream_t>(stream), timer_of(plan));
+  hipError_t e = pat::run_interp(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, grid, out,
+                                 static_cast<hipStream_t>(stream), timer_of(plan));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
 }
@@ -211,7 +215,8 @@ pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void
   if (s != PAT_OK) return s;
   if (!aligned16(values) || !aligned16(grid)) return set_err(PAT_ERR_INVALID_ARG, "values/grid NULL or not 16-byte aligned");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
-  hipError_t e = pat::run_spread(plan->prec, plan->inst, d, values, grid, static_cast<hipStream_t>(stream), timer_of(plan));
+  hipError_t e = pat::run_spread(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, values, grid,
+                                 static_cast<hipStream_t>(stream), timer_of(plan));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
 }

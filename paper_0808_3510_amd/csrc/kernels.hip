@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "launch.h"
 #include "pat_internal.h"
@@ -309,6 +310,25 @@ __device__ __forceinline__ void copy_batched(int total, Ld ld, St st) {
 }
 
 // ---------------------------------------------------------------------------
+// Work distribution
+
+struct StageArgs {
+  int32_t n;      // instances
+  int32_t total;  // work items over all instances
+  int32_t off[kMaxBatch + 1];
+  const Inst* inst[kMaxBatch];
+  const void* in[kMaxBatch];
+  void* out[kMaxBatch];
+  uint32_t* counter;  // persistent queue, or nullptr: item = blockIdx.x
+  int32_t len_nz;     // transverse passes: lines have nz (else nt) samples
+  int32_t mode;       // FFT direction (0 forward, 1 inverse) / interp, spread mode
+  int32_t pair_ok;    // pc holds every instance's mirrored tap-pair polynomials
+  // per tap pair p (taps t = p and taps-1-p): even part (powers x^0, x^2, ...)
+  // then odd part (x^1, x^3, ...) of tap p's polynomial, in the compute type
+  alignas(8) uint32_t pc[kPolyWords];
+};
+
+// ---------------------------------------------------------------------------
 // Kaiser-Bessel interpolation kernel.  With s = sqrt(K^2 - u^2), |u| <= K,
 //   Psi_hat(u) I0(alpha K) / (2 e^{alpha K}) = e^{alpha (s - K)} (1 - e^{-2 alpha s}) / (2 s)
 // (the transform of Section 3.2 with the large factor e^{alpha K} / I0(alpha K)
@@ -364,67 +384,100 @@ __device__ __forceinline__ cx<T> phase_mpi(double nu) {
   return mk(c, -s);
 }
 
-// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m].  TAPS > 0 fixes the
-// tap count at compile time: the grid values are read first and the TAPS
-// polynomials advance as independent Horner chains on workgroup-uniform
-// coefficients.
+// nu+ = sqrt(A) and 1/nu in double from a float estimate and one Newton step
+// (relative error ~1e-14, far cheaper than the correctly rounded operations).
+__device__ __forceinline__ double sqrt_nt(double A) {
+  const float s0 = sqrtf((float)A);
+  if (s0 == 0.0f) return 0.0;
+  const double s = (double)s0;
+  return fma(fma(-s, s, A), (double)(0.5f * __builtin_amdgcn_rcpf(s0)), s);
+}
+__device__ __forceinline__ double rcp_nt(double v) {
+  const double y = (double)__builtin_amdgcn_rcpf((float)v);
+  return y * fma(-v, y, 2.0);
+}
+
+// The TAPS tap weights of a node with offset x = 2 (delta - cK) + 1, from the
+// mirrored pairs in the kernel arguments: tap taps-1-t at x equals tap t at -x
+// (the kernel is even), so each pair costs one even and one odd polynomial
+// in x^2 on workgroup-uniform coefficients.
 template <typename T, int TAPS>
-__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, const Inst& I) {
-  const NodePos np = node_pos(nu, I.c, I.ck);
-  int j0 = np.j0 % m;
-  if (j0 < 0) j0 += m;
+__device__ __forceinline__ void tap_weights_pairs(const StageArgs& a, T x, T* w) {
+  constexpr int D = Deg<T>::v, NE = D / 2 + 1, NO = (D + 1) / 2, PW = NE + NO;
+  const T* pc = reinterpret_cast<const T*>(a.pc);
+  const T y = x * x;
+#pragma unroll
+  for (int p = 0; p < TAPS / 2; ++p) {
+    T e = pc[p * PW + NE - 1];
+#pragma unroll
+    for (int i = NE - 2; i >= 0; --i) e = e * y + pc[p * PW + i];
+    T o = pc[p * PW + NE + NO - 1];
+#pragma unroll
+    for (int i = NO - 2; i >= 0; --i) o = o * y + pc[p * PW + NE + i];
+    w[p] = e + x * o;
+    w[TAPS - 1 - p] = e - x * o;
+  }
+}
+
+// Weight of tap t for a node (general path): the fitted polynomial from the
+// instance table, or the kernel itself when no fit met the tolerance.
+template <typename T>
+__device__ __forceinline__ T tap_weight(const Inst& I, int t, T x) {
+  if (I.poly) return tap_poly<T>(static_cast<const T*>(I.poly_c) + t * (Deg<T>::v + 1), x);
+  const T delta = T(I.ck - 0.5) + T(0.5) * x;
+  return kb_phi<T>((delta - T(t)) * T(1.0 / I.c), T(I.K), T(I.alpha));
+}
+
+// Node quantities on the oversampled grid for nu (time-bin units):
+// first tap j0 = floor(c nu - cK) + 1 reduced mod m, polynomial offset
+// x = 2 (c nu - j0 - cK) + 1 in (-1, 1], and exp(-i pi nu).
+template <typename T>
+struct Node {
+  int j0;
+  T x;
+  cx<T> ph;
+};
+template <typename T>
+__device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m) {
+  const double xc = I.c * nu;
+  const double f = floor(xc - I.ck);
+  Node<T> nd;
+  nd.x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
+  int j0 = (int)f + 1;
+  j0 %= m;
+  nd.j0 = j0 < 0 ? j0 + m : j0;
+  nd.ph = phase_mpi<T>(nu);
+  return nd;
+}
+
+// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m].  With PAIRS the
+// grid line carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
+// U[j0 .. j0 + TAPS - 1] without wrapping.
+template <typename T, int TAPS, bool PAIRS>
+__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, const Inst& I, const StageArgs& a) {
+  const Node<T> nd = make_node<T>(nu, I, m);
   cx<T> acc = mk(T(0), T(0));
-  constexpr int D = Deg<T>::v;
-  constexpr int D1 = D + 1;
-  if (TAPS > 0 && I.poly) {
-    constexpr int NT = TAPS > 0 ? TAPS : 1;
-    cx<T> g[NT];
+  if constexpr (PAIRS) {
+    T w[TAPS];
+    tap_weights_pairs<T, TAPS>(a, nd.x, w);
+    const cx<T>* u = U + nd.j0;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      int j = j0 + t;
-      if (j >= m) j -= m;
-      g[t] = U[j];
-    }
-    const T x = (T)(2.0 * (np.delta - I.ck) + 1.0);
-    const T* __restrict__ pc = static_cast<const T*>(I.poly_c);
-    T w[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) w[t] = pc[t * D1 + D];
-#pragma unroll
-    for (int d = D - 1; d >= 0; --d) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) w[t] = w[t] * x + pc[t * D1 + d];
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      acc.x += w[t] * g[t].x;
-      acc.y += w[t] * g[t].y;
+    for (int t = 0; t < TAPS; ++t) {
+      const cx<T> g = u[t];
+      acc.x += w[t] * g.x;
+      acc.y += w[t] * g.y;
     }
   } else {
-    const int taps = I.taps;
-    int jm = j0;
-    if (I.poly) {
-      const T x = (T)(2.0 * (np.delta - I.ck) + 1.0);
-      const T* pc = static_cast<const T*>(I.poly_c);
-      for (int t = 0; t < taps; ++t) {
-        const T w = tap_poly<T>(pc + t * D1, x);
-        const cx<T> g = U[jm];
-        acc.x += w * g.x;
-        acc.y += w * g.y;
-        if (++jm == m) jm = 0;
-      }
-    } else {
-      const T delta = (T)np.delta, cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha);
-      for (int t = 0; t < taps; ++t) {
-        const T w = kb_phi<T>((delta - T(t)) * cinv, K, alpha);
-        const cx<T> g = U[jm];
-        acc.x += w * g.x;
-        acc.y += w * g.y;
-        if (++jm == m) jm = 0;
-      }
+    int jm = nd.j0;
+    for (int t = 0; t < I.taps; ++t) {
+      const T w = tap_weight<T>(I, t, nd.x);
+      const cx<T> g = U[jm];
+      acc.x += w * g.x;
+      acc.y += w * g.y;
+      if (++jm == m) jm = 0;
     }
   }
-  return cmul(acc, phase_mpi<T>(nu));
+  return cmul(acc, nd.ph);
 }
 
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
@@ -434,35 +487,38 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
   return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
 }
 
-// a3 over a group of nl lines whose grids sit in LDS in natural order
-// (U + b*m).  mode 0 (R): node sign(l) nu+, weight wcoef |l| / nu+ (0 at
+// a3 over a group of nl lines whose grids sit in LDS in natural order at
+// U + b*ls.  mode 0 (R): node sign(l) nu+, weight wcoef |l| / nu+ (0 at
 // l = 0), mean of the nodes -+nu+ on l = -nz/2.  mode 1 (A^T): mean of the
-// nodes +-nu+ for every l, no weight.  put(e, value) receives output e = b*nz + l_index.
-template <typename T, int TAPS, typename Put>
-__device__ __forceinline__ void interp_lines(const Inst& I, const cx<T>* U, int line0, int nl, int mode, Put put) {
+// nodes +-nu+ for every l, no weight.  put(e, value) receives output
+// e = b*nz + l_index.
+template <typename T, int TAPS, bool PAIRS, typename Put>
+__device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls, int line0,
+                                             int nl, int mode, Put put) {
   const int m = I.m, nz = I.nz;
+  const double wsc = I.wcoef * I.scale;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
     const int b = e / nz;
     const int il = e - b * nz;
-    const cx<T>* Ub = U + b * m;
+    const cx<T>* Ub = U + b * ls;
     const double Ak = line_ak(I, line0 + b);
     const int l = 2 * il < nz ? il : il - nz;
-    const double nup = sqrt(Ak + I.b * (double)l * (double)l);
+    const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
     cx<T> v;
     if (mode == 0) {
       if (l == 0) {
         v = mk(T(0), T(0));
       } else {
-        const double w = I.wcoef * (double)(l < 0 ? -l : l) / nup * I.scale;
+        const double w = wsc * (double)(l < 0 ? -l : l) * rcp_nt(nup);
         if (2 * l == -nz) {
-          v = cadd(interp_eval<T, TAPS>(Ub, m, -nup, I), interp_eval<T, TAPS>(Ub, m, nup, I));
+          v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, -nup, I, a), interp_eval<T, TAPS, PAIRS>(Ub, m, nup, I, a));
           v = cscl(v, T(0.5 * w));
         } else {
-          v = cscl(interp_eval<T, TAPS>(Ub, m, l > 0 ? nup : -nup, I), T(w));
+          v = cscl(interp_eval<T, TAPS, PAIRS>(Ub, m, l > 0 ? nup : -nup, I, a), T(w));
         }
       }
     } else {
-      v = cadd(interp_eval<T, TAPS>(Ub, m, nup, I), interp_eval<T, TAPS>(Ub, m, -nup, I));
+      v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, nup, I, a), interp_eval<T, TAPS, PAIRS>(Ub, m, -nup, I, a));
       v = cscl(v, T(0.5 * I.scale));
     }
     put(e, v);
@@ -471,69 +527,58 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const cx<T>* U, int 
 
 // Type-1 spreading of one line, the transpose of interp_lines' sum.  The
 // line's nodes are listed in increasing order (monotone in l by construction)
-// with their first tap j0, polynomial offset x and value; a start table maps
-// each first-tap index v to the first node with j0 >= v, so grid cell j (and
-// each periodic image j + q m) gathers exactly the nodes with j0 in
-// (j - taps, j], in node order: no atomics, deterministic.
+// with their first tap j0 (unreduced), value and the taps tap weights, computed
+// once per node; a start table maps each first-tap index v to the first node
+// with j0 >= v, so grid cell j (and each periodic image j + q m) gathers
+// exactly the nodes with j0 in (j - taps, j], in node order: no atomics,
+// deterministic.
 //   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
 //     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
 //     whose value feeds both -nu+ and +nu+.
 //   mode 1 (A): nodes -nu+(nz/2) .. -nu+(0), +nu+(0) .. +nu+(nz/2); value
 //     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
-// Fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
+// fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
 template <typename T>
 struct SpreadLds {
   cx<T>* val;
-  T* xs;
-  T* coef;
+  T* wts;
   int* j0s;
   int* start;
   static __device__ __forceinline__ SpreadLds carve(void* base, int nz, int taps) {
-    constexpr int D1 = Deg<T>::v + 1;
     SpreadLds s;
     const int nn = nz + 2;
     s.val = static_cast<cx<T>*>(base);
-    s.xs = reinterpret_cast<T*>(s.val + nn);
-    s.coef = s.xs + nn;
-    s.j0s = reinterpret_cast<int*>(s.coef + taps * D1);
+    s.wts = reinterpret_cast<T*>(s.val + nn);
+    s.j0s = reinterpret_cast<int*>(s.wts + nn * taps);
     s.start = s.j0s + nn;
     return s;
   }
-  static size_t bytes(int nz, int taps, int span_max) {
-    constexpr int D1 = Deg<T>::v + 1;
-    return ((size_t)nz + 2) * (sizeof(cx<T>) + sizeof(T) + sizeof(int)) + (size_t)taps * D1 * sizeof(T) +
-           ((size_t)span_max + 2) * sizeof(int);
-  }
 };
 
-template <typename T, typename Fget, typename Put>
-__device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, SpreadLds<T> L, Fget fget, Put put) {
-  const int m = I.m, nz = I.nz, taps = I.taps;
-  constexpr int D1 = Deg<T>::v + 1;
+template <typename T, int TAPS, bool PAIRS, typename Fget, typename Put>
+__device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, int line, int mode, SpreadLds<T> L,
+                                            Fget fget, Put put) {
+  const int m = I.m, nz = I.nz, taps = PAIRS ? TAPS : I.taps;
   const int nn = mode == 0 ? nz + 1 : nz + 2;
   const double Ak = line_ak(I, line);
   const int half = nz / 2;
-  if (I.poly) {
-    const T* pc = static_cast<const T*>(I.poly_c);
-    for (int i = threadIdx.x; i < taps * D1; i += kBlock) L.coef[i] = pc[i];
-  }
+  const double wsc = I.wcoef * I.scale;
   for (int i = threadIdx.x; i < nn; i += kBlock) {
     double nu, cf;
     cx<T> q;
     if (mode == 0) {
       const int l = i < nz ? i - half : half;
-      const double nup = sqrt(Ak + I.b * (double)l * (double)l);
+      const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
       const int lm = l < 0 ? l + nz : (l == half ? half : l);
       q = fget(lm);
       if (i == nz) {
         nu = nup;
-        cf = 0.5 * I.wcoef * (double)half / nup;
+        cf = 0.5 * wsc * (double)half * rcp_nt(nup);
       } else {
         nu = l > 0 ? nup : (l < 0 ? -nup : 0.0);
-        cf = l == 0 ? 0.0 : I.wcoef * (double)(l < 0 ? -l : l) / nup;
+        cf = l == 0 ? 0.0 : wsc * (double)(l < 0 ? -l : l) * rcp_nt(nup);
         if (l == -half) cf *= 0.5;
       }
-      cf *= I.scale;
     } else {
       int mp;
       double sg;
@@ -544,16 +589,26 @@ __device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, S
         mp = i - half - 1;
         sg = 1.0;
       }
-      const double nup = sqrt(Ak + I.b * (double)mp * (double)mp);
+      const double nup = sqrt_nt(Ak + I.b * (double)mp * (double)mp);
       nu = sg * nup;
       q = fget(mp);
       if (mp != 0 && mp != half) q = cadd(q, fget(nz - mp));
       cf = 0.5 * I.scale;
     }
-    const NodePos np = node_pos(nu, I.c, I.ck);
+    const double xc = I.c * nu;
+    const double f = floor(xc - I.ck);
+    const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
     L.val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
-    L.xs[i] = (T)(2.0 * (np.delta - I.ck) + 1.0);
-    L.j0s[i] = np.j0;
+    L.j0s[i] = (int)f + 1;
+    T* wi = L.wts + i * taps;
+    if constexpr (PAIRS) {
+      T w[TAPS];
+      tap_weights_pairs<T, TAPS>(a, x, w);
+#pragma unroll
+      for (int t = 0; t < TAPS; ++t) wi[t] = w[t];
+    } else {
+      for (int t = 0; t < taps; ++t) wi[t] = tap_weight<T>(I, t, x);
+    }
   }
   __syncthreads();
   const int jlo = L.j0s[0];
@@ -567,7 +622,6 @@ __device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, S
   if (threadIdx.x == 0) L.start[span] = nn;
   __syncthreads();
   const int jhi = jlo + span - 1 + taps - 1;
-  const T cinv = T(1.0 / I.c), K = T(I.K), alpha = T(I.alpha), ckh = T(I.ck - 0.5);
   for (int j = threadIdx.x; j < m; j += kBlock) {
     cx<T> acc = mk(T(0), T(0));
     // first periodic image j + q m that can be covered
@@ -581,13 +635,7 @@ __device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, S
       if (v0 > v1) continue;
       const int i1 = L.start[v1 + 1];
       for (int i = L.start[v0]; i < i1; ++i) {
-        const int t = jp - L.j0s[i];
-        T w;
-        if (I.poly) {
-          w = tap_poly<T>(L.coef + t * D1, L.xs[i]);
-        } else {
-          w = kb_phi<T>((ckh + T(0.5) * L.xs[i] - T(t)) * cinv, K, alpha);
-        }
+        const T w = L.wts[i * taps + (jp - L.j0s[i])];
         const cx<T> vv = L.val[i];
         acc.x += w * vv.x;
         acc.y += w * vv.y;
@@ -596,21 +644,6 @@ __device__ __forceinline__ void spread_line(const Inst& I, int line, int mode, S
     put(j, acc);
   }
 }
-
-// ---------------------------------------------------------------------------
-// Work distribution
-
-struct StageArgs {
-  int32_t n;      // instances
-  int32_t total;  // work items over all instances
-  int32_t off[kMaxBatch + 1];
-  const Inst* inst[kMaxBatch];
-  const void* in[kMaxBatch];
-  void* out[kMaxBatch];
-  uint32_t* counter;  // persistent queue, or nullptr: item = blockIdx.x
-  int32_t len_nz;     // transverse passes: lines have nz (else nt) samples
-  int32_t mode;       // FFT direction (0 forward, 1 inverse) / interp, spread mode
-};
 
 __device__ __forceinline__ int next_item(const StageArgs& a, int iter, int* s_item) {
   int item;
@@ -905,26 +938,44 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   const int m = I.m, nz = I.nz;
   const int line0 = li * I.lpw_i;
   const int nl = min(I.lpw_i, I.lines - line0);
+  const bool pairs = TAPS > 0 && a.pair_ok;
+  const int H = pairs ? TAPS - 1 : 0;
+  const int ls = m + H;
   const G* grid = static_cast<const G*>(a.in[inst_]);
   copy_batched<4>(
       nl * m, [&](int e) { return GridIO<T, G>::ld(grid, (size_t)line0 * m + e); },
-      [&](int e, cx<T> v) { buf[e] = v; });
+      [&](int e, cx<T> v) {
+        const int b = e / m;
+        const int j = e - b * m;
+        buf[b * ls + j] = v;
+        if (j < H) buf[b * ls + m + j] = v;
+      });
   __syncthreads();
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
-  interp_lines<T, TAPS>(I, buf, line0, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
+  if (pairs) {
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true>(I, a, buf, ls, line0, nl, a.mode,
+                                                 [&](int e, cx<T> v) { out[e] = v; });
+  } else {
+    interp_lines<T, 0, false>(I, a, buf, ls, line0, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
+  }
   PAT_END_ITEM
 }
 
 // spreading alone: depth spectra from memory, grid lines to memory.
-template <typename T, typename G>
+template <typename T, typename G, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
   PAT_FOR_EACH_ITEM(a)
   const SpreadLds<T> L = SpreadLds<T>::carve(pat_smem, I.nz, I.taps);
   const cx<T>* F = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * I.nz;
   G* grid = static_cast<G*>(a.out[inst_]);
   const size_t row = (size_t)li * I.m;
-  spread_line<T>(
-      I, li, a.mode, L, [&](int l) { return F[l]; }, [&](int j, cx<T> v) { GridIO<T, G>::st(grid, row + j, v); });
+  auto fget = [&](int l) { return F[l]; };
+  auto put = [&](int j, cx<T> v) { GridIO<T, G>::st(grid, row + j, v); };
+  if (TAPS > 0 && a.pair_ok) {
+    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put);
+  } else {
+    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put);
+  }
   PAT_END_ITEM
 }
 
@@ -939,9 +990,12 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   const int lpw = I.lpw_f;
   const int line0 = li * lpw;
   const int nl = min(lpw, I.lines - line0);
+  const bool pairs = TAPS > 0 && a.pair_ok;
+  const int H = pairs ? TAPS - 1 : 0;
+  const int ls = m + H;
   const int sp = m > nz ? m : nz;
   cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
-  cx<T>* gn = gp + lpw * sp;                         // grid in natural order
+  cx<T>* gn = gp + lpw * sp;                         // grid in natural order, with halo
   load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, gp);
   __syncthreads();
   fft_lds<T, P2, true>(gp, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
@@ -949,11 +1003,18 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
     int b, j;
     divmod<P2>(e, m, &b, &j);
-    gn[e] = gp[b * m + permm[j]];
+    const cx<T> v = gp[b * m + permm[j]];
+    gn[b * ls + j] = v;
+    if (j < H) gn[b * ls + m + j] = v;
   }
   __syncthreads();
   cx<T>* fz = gp;  // the permuted grid is no longer needed
-  interp_lines<T, TAPS>(I, gn, line0, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
+  if (pairs) {
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true>(I, a, gn, ls, line0, nl, a.mode,
+                                                 [&](int e, cx<T> v) { fz[e] = cconj(v); });
+  } else {
+    interp_lines<T, 0, false>(I, a, gn, ls, line0, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
+  }
   __syncthreads();
   fft_lds<T, P2, true>(fz, I.fz, static_cast<const cx<T>*>(I.tw), nl, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
@@ -968,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
 
 // Fused depth DFT + spreading + transposed a2 (operators R^T and A): one line
 // per work item; only the depth line is loaded and only the time line stored.
-template <typename T, bool P2>
+template <typename T, bool P2, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz, nt = I.nt;
@@ -980,8 +1041,13 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   __syncthreads();
   fft_lds<T, P2, true>(q, I.fz, static_cast<const cx<T>*>(I.tw), 1, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
-  spread_line<T>(
-      I, li, a.mode, L, [&](int l) { return q[permz[l]]; }, [&](int j, cx<T> v) { grid[j] = cconj(v); });
+  auto fget = [&](int l) { return q[permz[l]]; };
+  auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
+  if (TAPS > 0 && a.pair_ok) {
+    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put);
+  } else {
+    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put);
+  }
   __syncthreads();
   ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt);
   PAT_END_ITEM
@@ -1054,6 +1120,7 @@ struct Runner {
   int n;
   const Inst* h;
   const Inst* const* d;
+  const void* const* hp;  // host tap-polynomial tables
   uint32_t* counters;
   int next_counter;
   hipStream_t st;
@@ -1075,7 +1142,28 @@ struct Runner {
     }
     a.total = a.off[n];
     a.counter = counters ? counters + (next_counter++ % kNumCounters) : nullptr;
+    fill_pairs(a);
     return a;
+  }
+
+  // Mirrored tap-pair coefficients into the arguments when every instance
+  // uses the same fitted table with TAPS (even) taps.
+  void fill_pairs(StageArgs& a) const {
+    a.pair_ok = 0;
+    constexpr int D = Deg<T>::v, D1 = D + 1, NE = D / 2 + 1, NO = (D + 1) / 2, PW = NE + NO;
+    if (TAPS <= 0 || TAPS % 2 != 0 || (size_t)(TAPS / 2) * PW * sizeof(T) > sizeof(a.pc) || !hp) return;
+    for (int i = 0; i < n; ++i) {
+      if (!h[i].poly || h[i].taps != TAPS || !hp[i]) return;
+      if (std::memcmp(hp[i], hp[0], (size_t)TAPS * D1 * sizeof(T)) != 0) return;
+    }
+    const T* mono = static_cast<const T*>(hp[0]);
+    T pc[(TAPS > 0 ? TAPS / 2 : 1) * PW];
+    for (int p = 0; p < TAPS / 2; ++p) {
+      for (int e = 0; e < NE; ++e) pc[p * PW + e] = mono[p * D1 + 2 * e];
+      for (int o = 0; o < NO; ++o) pc[p * PW + NE + o] = mono[p * D1 + 2 * o + 1];
+    }
+    std::memcpy(a.pc, pc, sizeof(pc));
+    a.pair_ok = 1;
   }
 
   template <typename F>
@@ -1090,57 +1178,53 @@ struct Runner {
 
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
-    return launch(k_tr_x1_r2c<T, P2>, "dft_x1", a, max_over([](const Inst& I) { return (size_t)I.n1 * I.tb * cs; }),
-                  st, tm);
+    return launch(k_tr_x1_r2c<T, P2>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
+                  tm);
   }
   hipError_t x2(void* const* io, bool nz, int inv) {
     StageArgs a = base(IT_X2, nz, inv, io, io);
     return launch(k_tr_x2<T, P2>, inv ? "idft_x2" : "dft_x2", a,
-                  max_over([](const Inst& I) { return (size_t)I.n2 * I.tb * cs; }), st, tm);
+                  max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
   }
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_C2R, nz, 0, in, out);
-    return launch(k_tr_c2r_k1<T, P2>, "idft_x1_c2r", a,
-                  max_over([](const Inst& I) { return (size_t)I.n1 * I.tb * cs; }), st, tm);
+    return launch(k_tr_c2r_k1<T, P2>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
+                  st, tm);
   }
   hipError_t zfft(void* const* io, int inv) {
     StageArgs a = base(IT_LZ, true, inv, io, io);
     return launch(k_line_fft<T, P2>, inv ? "idft_z" : "dft_z", a,
-                  max_over([](const Inst& I) { return (size_t)I.lpw_z * I.nz * cs; }), st, tm);
+                  max_over([](const Inst& I) { return lds_line_z(I, cs); }), st, tm);
   }
   hipError_t a2(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
-    return launch(k_line_a2<T, G, P2>, "deconv_pad_fft", a,
-                  max_over([](const Inst& I) { return (size_t)I.lpw_m * I.m * cs; }), st, tm);
+    return launch(k_line_a2<T, G, P2>, "deconv_pad_fft", a, max_over([](const Inst& I) { return lds_line_m(I, cs); }),
+                  st, tm);
   }
   hipError_t a2t(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
     return launch(k_line_a2t<T, G, P2>, "ifft_pick_deconv", a,
-                  max_over([](const Inst& I) { return (size_t)I.lpw_m * I.m * cs; }), st, tm);
+                  max_over([](const Inst& I) { return lds_line_m(I, cs); }), st, tm);
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LI, true, mode, in, out);
     return launch(k_line_interp<T, G, TAPS>, "interp", a,
-                  max_over([](const Inst& I) { return (size_t)I.lpw_i * I.m * cs; }), st, tm);
+                  max_over([](const Inst& I) { return lds_interp(I, cs); }), st, tm);
   }
   hipError_t spread(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LINE, true, mode, in, out);
-    return launch(k_line_spread<T, G>, "spread", a,
-                  max_over([](const Inst& I) { return SpreadLds<T>::bytes(I.nz, I.taps, I.span_max) + 64; }), st,
-                  tm);
+    return launch(k_line_spread<T, G, TAPS>, "spread", a,
+                  max_over([](const Inst& I) { return lds_spread(I, cs); }), st, tm);
   }
   hipError_t nufft2(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LF, true, mode, in, out);
     return launch(k_line_nufft2<T, P2, TAPS>, "nufft_fused", a,
-                  max_over([](const Inst& I) { return (size_t)I.lpw_f * (I.m + (I.m > I.nz ? I.m : I.nz)) * cs; }),
-                  st, tm);
+                  max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LINE, true, mode, in, out);
-    return launch(k_line_nufft1<T, P2>, "nufft_adjoint_fused", a, max_over([](const Inst& I) {
-                    return ((size_t)I.m + I.nz) * cs + SpreadLds<T>::bytes(I.nz, I.taps, I.span_max) + 64;
-                  }),
-                  st, tm);
+    return launch(k_line_nufft1<T, P2, TAPS>, "nufft_adjoint_fused", a,
+                  max_over([](const Inst& I) { return lds_fused1(I, cs); }), st, tm);
   }
 };
 
@@ -1151,9 +1235,9 @@ struct Runner {
   } while (0)
 
 template <typename T, typename G, bool P2, int TAPS>
-hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
-                    void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  Runner<T, G, P2, TAPS> r{n, h, d, counters, 0, st, tm};
+hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
+                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
+  Runner<T, G, P2, TAPS> r{n, h, d, hp, counters, 0, st, tm};
   void* bg[kMaxBatch];
   void* bu[kMaxBatch];
   void* bf[kMaxBatch];
@@ -1217,71 +1301,79 @@ bool all_taps(int n, const Inst* h, int taps) {
 }
 
 template <typename T, typename G>
-hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* in, void* const* out,
-                    void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
+hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
+                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
   const bool t12 = all_taps(n, h, 12);
   if (all_pow2(n, h)) {
-    if (t12) return run_op_t<T, G, true, 12>(op, n, h, d, in, out, ws, counters, st, tm);
-    return run_op_t<T, G, true, 0>(op, n, h, d, in, out, ws, counters, st, tm);
+    if (t12) return run_op_t<T, G, true, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+    return run_op_t<T, G, true, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
   }
-  if (t12) return run_op_t<T, G, false, 12>(op, n, h, d, in, out, ws, counters, st, tm);
-  return run_op_t<T, G, false, 0>(op, n, h, d, in, out, ws, counters, st, tm);
+  if (t12) return run_op_t<T, G, false, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  return run_op_t<T, G, false, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
 }
 
 template <typename T, typename G>
-hipError_t interp_only(const Inst& h, const Inst* dinst, const void* grid, void* out, hipStream_t st, StageTimer* tm) {
+hipError_t interp_only(const Inst& h, const Inst* dinst, const void* hpoly, const void* grid, void* out,
+                       hipStream_t st, StageTimer* tm) {
   const Inst* d[1] = {dinst};
+  const void* hp[1] = {hpoly};
   const void* in[1] = {grid};
   void* o[1] = {out};
   if (h.taps == 12) {
-    Runner<T, G, false, 12> r{1, &h, d, nullptr, 0, st, tm};
+    Runner<T, G, false, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
     return r.interp(in, o, 0);
   }
-  Runner<T, G, false, 0> r{1, &h, d, nullptr, 0, st, tm};
+  Runner<T, G, false, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
   return r.interp(in, o, 0);
 }
 
 template <typename T, typename G>
-hipError_t spread_only(const Inst& h, const Inst* dinst, const void* vals, void* grid, hipStream_t st,
-                       StageTimer* tm) {
+hipError_t spread_only(const Inst& h, const Inst* dinst, const void* hpoly, const void* vals, void* grid,
+                       hipStream_t st, StageTimer* tm) {
   const Inst* d[1] = {dinst};
+  const void* hp[1] = {hpoly};
   const void* in[1] = {vals};
   void* o[1] = {grid};
-  Runner<T, G, false, 0> r{1, &h, d, nullptr, 0, st, tm};
+  if (h.taps == 12) {
+    Runner<T, G, false, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+    return r.spread(in, o, 0);
+  }
+  Runner<T, G, false, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
   return r.spread(in, o, 0);
 }
 
 }  // namespace
 
-hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* in,
-                  void* const* out, void* const* ws, uint32_t* counters, hipStream_t stream, StageTimer* timer) {
+hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* hpoly,
+                  const void* const* in, void* const* out, void* const* ws, uint32_t* counters, hipStream_t stream,
+                  StageTimer* timer) {
   switch (prec) {
     case PREC_F64:
-      return dispatch<double, cx<double>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<double, cx<double>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
     case PREC_F32:
-      return dispatch<float, cx<float>>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<float, cx<float>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
     case PREC_BF16:
-      return dispatch<float, bf2>(op, n, hinst, dinst, in, out, ws, counters, stream, timer);
+      return dispatch<float, bf2>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* grid, void* out, hipStream_t stream,
-                      StageTimer* timer) {
+hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* grid, void* out,
+                      hipStream_t stream, StageTimer* timer) {
   switch (prec) {
-    case PREC_F64: return interp_only<double, cx<double>>(hinst, dinst, grid, out, stream, timer);
-    case PREC_F32: return interp_only<float, cx<float>>(hinst, dinst, grid, out, stream, timer);
-    case PREC_BF16: return interp_only<float, bf2>(hinst, dinst, grid, out, stream, timer);
+    case PREC_F64: return interp_only<double, cx<double>>(hinst, dinst, hpoly, grid, out, stream, timer);
+    case PREC_F32: return interp_only<float, cx<float>>(hinst, dinst, hpoly, grid, out, stream, timer);
+    case PREC_BF16: return interp_only<float, bf2>(hinst, dinst, hpoly, grid, out, stream, timer);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* vals, void* grid, hipStream_t stream,
-                      StageTimer* timer) {
+hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* vals, void* grid,
+                      hipStream_t stream, StageTimer* timer) {
   switch (prec) {
-    case PREC_F64: return spread_only<double, cx<double>>(hinst, dinst, vals, grid, stream, timer);
-    case PREC_F32: return spread_only<float, cx<float>>(hinst, dinst, vals, grid, stream, timer);
-    case PREC_BF16: return spread_only<float, bf2>(hinst, dinst, vals, grid, stream, timer);
+    case PREC_F64: return spread_only<double, cx<double>>(hinst, dinst, hpoly, vals, grid, stream, timer);
+    case PREC_F32: return spread_only<float, cx<float>>(hinst, dinst, hpoly, vals, grid, stream, timer);
+    case PREC_BF16: return spread_only<float, bf2>(hinst, dinst, hpoly, vals, grid, stream, timer);
   }
   return hipErrorInvalidValue;
 }

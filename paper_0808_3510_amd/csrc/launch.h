@@ -18,20 +18,21 @@ struct StageTimer {
 };
 
 // One operator over n instances.  hinst: host copies of the descriptors,
-// dinst: their device addresses.  in/out: user arrays; ws: per-instance
-// workspace bases.  counters: kNumCounters zeroed words of device memory for
-// the persistent work queue, or nullptr for one workgroup per work item.
-hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst,
+// dinst: their device addresses, hpoly: host copies of their tap-polynomial
+// tables.  in/out: user arrays; ws: per-instance workspace bases.  counters:
+// kNumCounters zeroed words of device memory for the persistent work queue,
+// or nullptr for one workgroup per work item.
+hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* hpoly,
                   const void* const* in, void* const* out, void* const* ws, uint32_t* counters,
                   hipStream_t stream, StageTimer* timer);
 
 // Stage a3 alone on user buffers (grid in, weighted node values out).
-hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* grid, void* out,
-                      hipStream_t stream, StageTimer* timer);
+hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* grid,
+                      void* out, hipStream_t stream, StageTimer* timer);
 
 // Spreading alone (operator R^T's type-1 step) on user buffers: depth
 // spectra in, oversampled grid lines out.
-hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* vals, void* grid,
-                      hipStream_t stream, StageTimer* timer);
+hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* vals,
+                      void* grid, hipStream_t stream, StageTimer* timer);
 
 }  // namespace pat

@@ -15,8 +15,10 @@ constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
 // Degree of the per-tap polynomial that replaces the kernel evaluation
 // (float and double paths).
-constexpr int kPolyDegF = 9;
+constexpr int kPolyDegF = 8;
 constexpr int kPolyDegD = 15;
+// 32-bit words of the mirrored tap-pair coefficients passed in kernel arguments
+constexpr int kPolyWords = 192;
 
 // One FFT length: in-place decimation-in-frequency mixed-radix factorisation.
 // After the transform the natural-order bin k sits at LDS position perm[k].
@@ -59,9 +61,30 @@ struct Inst {
   int64_t off_g, off_u, off_f;
 };
 
-// Host-side plan (see pat.h).
-struct HostTables {
-  size_t desc_off, tw_off, perm_off, sn_off, total;
-};
+// LDS bytes each kernel needs for one instance (cs: bytes per complex
+// element, rs: per real).  The kernels carve their LDS exactly as described
+// here; the host plan uses the same functions for its capacity checks and the
+// launchers for the dynamic LDS request.
+inline size_t lds_tile_x1(const Inst& I, size_t cs) { return (size_t)I.n1 * I.tb * cs; }
+inline size_t lds_tile_x2(const Inst& I, size_t cs) { return (size_t)I.n2 * I.tb * cs; }
+inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.lpw_z * I.nz * cs; }
+inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.lpw_m * I.m * cs; }
+// interp: lpw_i grid lines of m entries plus a halo of taps - 1
+inline size_t lds_interp(const Inst& I, size_t cs) { return (size_t)I.lpw_i * ((size_t)I.m + I.taps) * cs; }
+// spreading lists: node values, per-node tap weights, first taps, start table
+inline size_t lds_spread_lists(int nz, int taps, int span_max, size_t cs, size_t rs) {
+  return ((size_t)nz + 2) * (cs + (size_t)taps * rs + sizeof(int32_t)) + ((size_t)span_max + 2) * sizeof(int32_t);
+}
+inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, I.span_max, cs, cs / 2); }
+// fused type-2 line kernel: lpw_f lines of max(m, nz) (FFT scratch, then the
+// depth line) and lpw_f grid lines of m + taps (natural order with halo)
+inline size_t lds_fused2(const Inst& I, size_t cs) {
+  const size_t sp = (size_t)(I.m > I.nz ? I.m : I.nz);
+  return (size_t)I.lpw_f * (sp + (size_t)I.m + I.taps) * cs;
+}
+// fused type-1 line kernel: one grid line, one depth line, the lists
+inline size_t lds_fused1(const Inst& I, size_t cs) {
+  return ((size_t)I.m + I.nz) * cs + lds_spread(I, cs);
+}
 
 }  // namespace pat

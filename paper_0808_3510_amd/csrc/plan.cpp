@@ -271,10 +271,9 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.lpw_m = clampi(2048 / m, 1, 16);
   I.lpw_z = clampi(2048 / g.nz, 1, 16);
   I.lpw_i = clampi(kBlock / g.nz, 1, 8);
-  while (I.lpw_i > 1 && (size_t)I.lpw_i * m * cs > 65536) --I.lpw_i;
+  while (I.lpw_i > 1 && lds_interp(I, cs) > 65536) --I.lpw_i;
   I.lpw_f = clampi(2048 / m, 1, 16);
-  const size_t fused_row = ((size_t)m + (size_t)(m > g.nz ? m : g.nz)) * cs;
-  while (I.lpw_f > 1 && (size_t)I.lpw_f * fused_row > 65536) --I.lpw_f;
+  while (I.lpw_f > 1 && lds_fused2(I, cs) > 65536) --I.lpw_f;
   I.c = g.c;
   I.K = g.K;
   I.alpha = g.alpha;
@@ -314,14 +313,11 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   const int deg = prec == PAT_F64 ? kPolyDegD : kPolyDegF;
   std::vector<double> coef;
   const double fit_err = fit_tap_polys(g.c, g.K, g.alpha, taps, deg, &coef);
-  I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 1e-8) ? 1 : 0;
+  I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 5e-8) ? 1 : 0;
   {
-    // LDS of the fused adjoint line kernel: depth spectrum, node lists,
-    // tap polynomials, start table and one grid line
-    const size_t lds_spread = (size_t)g.nz * cs + ((size_t)g.nz + 2) * (cs + rs + 4) +
-                              (size_t)taps * (deg + 1) * rs + ((size_t)I.span_max + 2) * 4 + (size_t)m * cs + 64;
-    // the bf16 option stores the oversampled grid, so it runs the staged kernels
-    I.fused = (prec != PAT_F32_BF16GRID && lds_spread <= 65536 && fused_row <= 131072) ? 1 : 0;
+    // the bf16 option stores the oversampled grid, so it runs the staged
+    // kernels; the fused ones need their LDS within one workgroup's share
+    I.fused = (prec != PAT_F32_BF16GRID && lds_fused1(I, cs) <= 65536 && lds_fused2(I, cs) <= 131072) ? 1 : 0;
   }
   const size_t off_poly = off;
   off = align256(off + coef.size() * rs);
