@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -199,6 +201,12 @@ def main():
     nt, nz = g["nt"], g["nz"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def run_prec(prec):
         plan = pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], precision=prec, device=dev)
