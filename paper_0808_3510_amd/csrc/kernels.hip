@@ -387,7 +387,7 @@ __device__ __forceinline__ cx<T> phase_mpi(double nu) {
 // nu+ = sqrt(A) and 1/nu in double from a float estimate and one Newton step
 // (relative error ~1e-14, far cheaper than the correctly rounded operations).
 __device__ __forceinline__ double sqrt_nt(double A) {
-  const float s0 = sqrtf((float)A);
+  const float s0 = __builtin_amdgcn_sqrtf((float)A);
   if (s0 == 0.0f) return 0.0;
   const double s = (double)s0;
   return fma(fma(-s, s, A), (double)(0.5f * __builtin_amdgcn_rcpf(s0)), s);
@@ -438,14 +438,17 @@ struct Node {
   cx<T> ph;
 };
 template <typename T>
-__device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m) {
+__device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, double inv_m) {
   const double xc = I.c * nu;
   const double f = floor(xc - I.ck);
   Node<T> nd;
   nd.x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
-  int j0 = (int)f + 1;
-  j0 %= m;
-  nd.j0 = j0 < 0 ? j0 + m : j0;
+  // (f + 1) mod m without an integer division
+  const double j1 = f + 1.0;
+  int j0 = (int)(j1 - (double)m * floor(j1 * inv_m));
+  if (j0 >= m) j0 -= m;
+  if (j0 < 0) j0 += m;
+  nd.j0 = j0;
   nd.ph = phase_mpi<T>(nu);
   return nd;
 }
@@ -454,8 +457,9 @@ __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m) {
 // grid line carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
 // U[j0 .. j0 + TAPS - 1] without wrapping.
 template <typename T, int TAPS, bool PAIRS>
-__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, const Inst& I, const StageArgs& a) {
-  const Node<T> nd = make_node<T>(nu, I, m);
+__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double inv_m, double nu, const Inst& I,
+                                             const StageArgs& a) {
+  const Node<T> nd = make_node<T>(nu, I, m, inv_m);
   cx<T> acc = mk(T(0), T(0));
   if constexpr (PAIRS) {
     T w[TAPS];
@@ -481,8 +485,8 @@ __device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double nu, c
 }
 
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
-  const int k1 = line / I.n2;
-  const int k2i = line - k1 * I.n2;
+  int k1, k2i;
+  divmod<false>(line, I.n2, &k1, &k2i);
   const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
   return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
 }
@@ -491,17 +495,18 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
 // U + b*ls.  mode 0 (R): node sign(l) nu+, weight wcoef |l| / nu+ (0 at
 // l = 0), mean of the nodes -+nu+ on l = -nz/2.  mode 1 (A^T): mean of the
 // nodes +-nu+ for every l, no weight.  put(e, value) receives output
-// e = b*nz + l_index.
-template <typename T, int TAPS, bool PAIRS, typename Put>
-__device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls, int line0,
-                                             int nl, int mode, Put put) {
+// e = b*nz + l_index.  akl[b] holds line b's |K_x|^2 term.
+template <typename T, int TAPS, bool PAIRS, bool P2, typename Put>
+__device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls,
+                                             const double* akl, int nl, int mode, Put put) {
   const int m = I.m, nz = I.nz;
   const double wsc = I.wcoef * I.scale;
+  const double inv_m = 1.0 / (double)m;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
-    const int b = e / nz;
-    const int il = e - b * nz;
+    int b, il;
+    divmod<P2>(e, nz, &b, &il);
     const cx<T>* Ub = U + b * ls;
-    const double Ak = line_ak(I, line0 + b);
+    const double Ak = akl[b];
     const int l = 2 * il < nz ? il : il - nz;
     const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
     cx<T> v;
@@ -511,14 +516,16 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
       } else {
         const double w = wsc * (double)(l < 0 ? -l : l) * rcp_nt(nup);
         if (2 * l == -nz) {
-          v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, -nup, I, a), interp_eval<T, TAPS, PAIRS>(Ub, m, nup, I, a));
+          v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, -nup, I, a),
+                   interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, nup, I, a));
           v = cscl(v, T(0.5 * w));
         } else {
-          v = cscl(interp_eval<T, TAPS, PAIRS>(Ub, m, l > 0 ? nup : -nup, I, a), T(w));
+          v = cscl(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, l > 0 ? nup : -nup, I, a), T(w));
         }
       }
     } else {
-      v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, nup, I, a), interp_eval<T, TAPS, PAIRS>(Ub, m, -nup, I, a));
+      v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, nup, I, a),
+               interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, -nup, I, a));
       v = cscl(v, T(0.5 * I.scale));
     }
     put(e, v);
@@ -526,12 +533,14 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 }
 
 // Type-1 spreading of one line, the transpose of interp_lines' sum.  The
-// line's nodes are listed in increasing order (monotone in l by construction)
-// with their first tap j0 (unreduced), value and the taps tap weights, computed
-// once per node; a start table maps each first-tap index v to the first node
-// with j0 >= v, so grid cell j (and each periodic image j + q m) gathers
-// exactly the nodes with j0 in (j - taps, j], in node order: no atomics,
-// deterministic.
+// line's nodes are listed in increasing order (monotone in l by construction);
+// for each node the taps contributions w_t * value (t < taps) are formed
+// once into LDS, with its first tap j0 (unreduced).  A start table maps each
+// first-tap index v (relative to the smallest) to the first node with
+// j0 >= v.  Grid cell j then gathers, for each periodic image and each tap t,
+// the nodes whose first tap is j - t: a contiguous node range read from two
+// neighbouring start entries, summed in node order.  No atomics and no
+// dependent loads; the result is deterministic.
 //   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
 //     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
 //     whose value feeds both -nu+ and +nu+.
@@ -540,8 +549,14 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 // fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
 template <typename T>
 struct SpreadLds {
-  cx<T>* val;
-  T* wts;
+  // Cells gathered per thread, and the zero padding on each side of a node's
+  // weight row that lets a block of kCells cells read kCells weights of any
+  // node in range without bounds tests.
+  static constexpr int kCells = 4;
+  static constexpr int kPad = kCells - 1;
+  static __host__ __device__ constexpr int row(int taps) { return ((taps + 2 * kPad + 3) / 4) * 4; }
+  cx<T>* val;  // [node] value
+  T* wts;      // [node][row] tap weights, tap t at kPad + t
   int* j0s;
   int* start;
   static __device__ __forceinline__ SpreadLds carve(void* base, int nz, int taps) {
@@ -549,7 +564,7 @@ struct SpreadLds {
     const int nn = nz + 2;
     s.val = static_cast<cx<T>*>(base);
     s.wts = reinterpret_cast<T*>(s.val + nn);
-    s.j0s = reinterpret_cast<int*>(s.wts + nn * taps);
+    s.j0s = reinterpret_cast<int*>(s.wts + nn * row(taps));
     s.start = s.j0s + nn;
     return s;
   }
@@ -600,48 +615,83 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
     const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
     L.val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
     L.j0s[i] = (int)f + 1;
-    T* wi = L.wts + i * taps;
+    constexpr int P = SpreadLds<T>::kPad;
+    const int rw = SpreadLds<T>::row(taps);
+    T* wi = L.wts + i * rw;
+    for (int t = 0; t < P; ++t) wi[t] = T(0);
+    for (int t = P + taps; t < rw; ++t) wi[t] = T(0);
     if constexpr (PAIRS) {
       T w[TAPS];
       tap_weights_pairs<T, TAPS>(a, x, w);
 #pragma unroll
-      for (int t = 0; t < TAPS; ++t) wi[t] = w[t];
+      for (int t = 0; t < TAPS; ++t) wi[P + t] = w[t];
     } else {
-      for (int t = 0; t < taps; ++t) wi[t] = tap_weight<T>(I, t, x);
+      for (int t = 0; t < taps; ++t) wi[P + t] = tap_weight<T>(I, t, x);
     }
   }
   __syncthreads();
   const int jlo = L.j0s[0];
   int span = L.j0s[nn - 1] - jlo + 1;
   span = span < I.span_max ? span : I.span_max;
-  for (int i = threadIdx.x; i < nn; i += kBlock) {
-    const int v0 = (i == 0 ? jlo : L.j0s[i - 1] + 1) - jlo;
-    const int v1 = L.j0s[i] - jlo;
-    for (int v = v0; v <= v1 && v < span; ++v) L.start[v] = i;
+  // start[v] for v in [0, span]: each thread fills a contiguous slice,
+  // locating its first node by binary search and walking forward (the
+  // evanescent band leaves gaps of hundreds of indices without nodes, so a
+  // per-node fill would leave single threads with most of the work)
+  {
+    const int per = (span + kBlock) / kBlock;
+    int v = (int)threadIdx.x * per;
+    const int vstop = v + per < span + 1 ? v + per : span + 1;
+    int lo = 0, hi = nn;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (L.j0s[mid] - jlo < v) lo = mid + 1;
+      else hi = mid;
+    }
+    for (; v < vstop; ++v) {
+      while (lo < nn && L.j0s[lo] - jlo < v) ++lo;
+      L.start[v] = lo;
+    }
   }
-  if (threadIdx.x == 0) L.start[span] = nn;
   __syncthreads();
-  const int jhi = jlo + span - 1 + taps - 1;
-  for (int j = threadIdx.x; j < m; j += kBlock) {
-    cx<T> acc = mk(T(0), T(0));
-    // first periodic image j + q m that can be covered
-    int q0 = jlo - j;
-    q0 = q0 >= 0 ? (q0 + m - 1) / m : -((-q0) / m);
-    for (int jp = j + q0 * m; jp <= jhi; jp += m) {
-      int v0 = jp - taps + 1 - jlo;
-      int v1 = jp - jlo;
-      v0 = v0 > 0 ? v0 : 0;
-      v1 = v1 < span - 1 ? v1 : span - 1;
-      if (v0 > v1) continue;
-      const int i1 = L.start[v1 + 1];
-      for (int i = L.start[v0]; i < i1; ++i) {
-        const T w = L.wts[i * taps + (jp - L.j0s[i])];
+  // Each thread owns kCells consecutive cells [j, j + kCells).  For every
+  // periodic image (offset v = j + q m - jlo of its first cell, with some
+  // cell of the block in [0, span + taps - 1)) the nodes touching the block
+  // have first taps in [v - taps + 1, v + kCells - 1]: one contiguous node
+  // range from two start entries.  Node i adds weight (v + c - (j0 - jlo))
+  // times its value to cell c; the padded weight row makes out-of-window taps
+  // read zeros.
+  constexpr int kCells = SpreadLds<T>::kCells;
+  constexpr int P = SpreadLds<T>::kPad;
+  const int rw = SpreadLds<T>::row(taps);
+  const int vend = span + taps - 1;
+  for (int j = kCells * (int)threadIdx.x; j < m; j += kCells * kBlock) {
+    cx<T> acc[kCells];
+#pragma unroll
+    for (int c = 0; c < kCells; ++c) acc[c] = mk(T(0), T(0));
+    int v = (j - jlo) % m;
+    if (v < 0) v += m;
+    // the image before may still reach the block's last cells
+    if (v - m + kCells - 1 >= 0) v -= m;
+    for (; v < vend; v += m) {
+      int lo = v - taps + 1, hi = v + kCells;
+      lo = lo < 0 ? 0 : (lo < span ? lo : span);
+      hi = hi < 0 ? 0 : (hi < span ? hi : span);
+      const int i1 = L.start[hi];
+      for (int i = L.start[lo]; i < i1; ++i) {
+        // taps t0 .. t0 + kCells - 1 with t0 = v - (j0 - jlo) in [-P, taps - 1]
+        const T* wr = L.wts + i * rw + (P + v - (L.j0s[i] - jlo));
         const cx<T> vv = L.val[i];
-        acc.x += w * vv.x;
-        acc.y += w * vv.y;
+#pragma unroll
+        for (int c = 0; c < kCells; ++c) {
+          const T w = wr[c];
+          acc[c].x += w * vv.x;
+          acc[c].y += w * vv.y;
+        }
       }
     }
-    put(j, acc);
+#pragma unroll
+    for (int c = 0; c < kCells; ++c)
+      if (j + c < m) put(j + c, acc[c]);
   }
 }
 
@@ -931,9 +981,10 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
 }
 
 // a3 alone: grid lines from memory, weighted node values to memory.
-template <typename T, typename G, int TAPS>
+template <typename T, typename G, int TAPS, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
+  __shared__ double s_ak[16];
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz;
   const int line0 = li * I.lpw_i;
@@ -950,13 +1001,14 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
         buf[b * ls + j] = v;
         if (j < H) buf[b * ls + m + j] = v;
       });
+  if (threadIdx.x < nl) s_ak[threadIdx.x] = line_ak(I, line0 + threadIdx.x);
   __syncthreads();
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
   if (pairs) {
-    interp_lines<T, (TAPS > 0 ? TAPS : 2), true>(I, a, buf, ls, line0, nl, a.mode,
-                                                 [&](int e, cx<T> v) { out[e] = v; });
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, buf, ls, s_ak, nl, a.mode,
+                                                     [&](int e, cx<T> v) { out[e] = v; });
   } else {
-    interp_lines<T, 0, false>(I, a, buf, ls, line0, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
+    interp_lines<T, 0, false, P2>(I, a, buf, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
   }
   PAT_END_ITEM
 }
@@ -985,6 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
 // node values are inverse-transformed over depth before the only store.
 template <typename T, bool P2, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
+  __shared__ double s_ak[16];
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nt = I.nt, nz = I.nz;
   const int lpw = I.lpw_f;
@@ -1007,13 +1060,14 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
     gn[b * ls + j] = v;
     if (j < H) gn[b * ls + m + j] = v;
   }
+  if (threadIdx.x < nl) s_ak[threadIdx.x] = line_ak(I, line0 + threadIdx.x);
   __syncthreads();
   cx<T>* fz = gp;  // the permuted grid is no longer needed
   if (pairs) {
-    interp_lines<T, (TAPS > 0 ? TAPS : 2), true>(I, a, gn, ls, line0, nl, a.mode,
-                                                 [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, gn, ls, s_ak, nl, a.mode,
+                                                     [&](int e, cx<T> v) { fz[e] = cconj(v); });
   } else {
-    interp_lines<T, 0, false>(I, a, gn, ls, line0, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    interp_lines<T, 0, false, P2>(I, a, gn, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
   }
   __syncthreads();
   fft_lds<T, P2, true>(fz, I.fz, static_cast<const cx<T>*>(I.tw), nl, nz, 1);
@@ -1208,7 +1262,7 @@ struct Runner {
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LI, true, mode, in, out);
-    return launch(k_line_interp<T, G, TAPS>, "interp", a,
+    return launch(k_line_interp<T, G, TAPS, P2>, "interp", a,
                   max_over([](const Inst& I) { return lds_interp(I, cs); }), st, tm);
   }
   hipError_t spread(const void* const* in, void* const* out, int mode) {
@@ -1320,6 +1374,10 @@ hipError_t interp_only(const Inst& h, const Inst* dinst, const void* hpoly, cons
   const void* in[1] = {grid};
   void* o[1] = {out};
   if (h.taps == 12) {
+    if (h.pow2) {
+      Runner<T, G, true, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+      return r.interp(in, o, 0);
+    }
     Runner<T, G, false, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
     return r.interp(in, o, 0);
   }

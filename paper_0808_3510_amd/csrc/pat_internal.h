@@ -13,6 +13,7 @@ constexpr int kMaxBatch = 32;    // instances in one batched call
 constexpr int kMaxTaps = 64;     // 2cK
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
+constexpr size_t kLdsMax = 160 * 1024;  // LDS of one CDNA4 compute unit
 // Degree of the per-tap polynomial that replaces the kernel evaluation
 // (float and double paths).
 constexpr int kPolyDegF = 8;
@@ -71,11 +72,13 @@ inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.lpw_z * I.
 inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.lpw_m * I.m * cs; }
 // interp: lpw_i grid lines of m entries plus a halo of taps - 1
 inline size_t lds_interp(const Inst& I, size_t cs) { return (size_t)I.lpw_i * ((size_t)I.m + I.taps) * cs; }
-// spreading lists: node values, per-node tap weights, first taps, start table
-inline size_t lds_spread_lists(int nz, int taps, int span_max, size_t cs, size_t rs) {
-  return ((size_t)nz + 2) * (cs + (size_t)taps * rs + sizeof(int32_t)) + ((size_t)span_max + 2) * sizeof(int32_t);
+// spreading lists: per-node value, zero-padded tap-weight row (taps + 6
+// entries rounded up to a multiple of 4), first tap; start table
+inline size_t lds_spread_lists(int nz, int taps, int span_max, size_t cs) {
+  const size_t row = (size_t)((taps + 6 + 3) / 4) * 4;
+  return ((size_t)nz + 2) * (cs + row * (cs / 2) + sizeof(int32_t)) + ((size_t)span_max + 2) * sizeof(int32_t);
 }
-inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, I.span_max, cs, cs / 2); }
+inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, I.span_max, cs); }
 // fused type-2 line kernel: lpw_f lines of max(m, nz) (FFT scratch, then the
 // depth line) and lpw_f grid lines of m + taps (natural order with halo)
 inline size_t lds_fused2(const Inst& I, size_t cs) {

@@ -230,7 +230,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   const int prec = g.precision;
   const size_t cs = complex_bytes(prec);
   const size_t rs = cs / 2;
-  if (2 * (size_t)m * cs > 131072) {
+  if ((size_t)m * cs > 65536) {
     msg << "c*nt = " << m << " exceeds the LDS line capacity for this precision";
     return fail(PAT_ERR_UNSUPPORTED);
   }
@@ -317,7 +317,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   {
     // the bf16 option stores the oversampled grid, so it runs the staged
     // kernels; the fused ones need their LDS within one workgroup's share
-    I.fused = (prec != PAT_F32_BF16GRID && lds_fused1(I, cs) <= 65536 && lds_fused2(I, cs) <= 131072) ? 1 : 0;
+    I.fused = (prec != PAT_F32_BF16GRID && lds_fused1(I, cs) <= kLdsMax && lds_fused2(I, cs) <= kLdsMax) ? 1 : 0;
   }
   const size_t off_poly = off;
   off = align256(off + coef.size() * rs);
