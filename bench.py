@@ -277,6 +277,15 @@ def main():
         plan.reconstruct_adjoint(q, out=pt)
     torch.cuda.synchronize()
     out["adjoint_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+    plan.set_timing(True)
+    plan.stage_times()
+    for _ in range(args.steps):
+        plan.reconstruct_adjoint(q, out=pt)
+    acc = {}
+    for name, ms_ in plan.stage_times():
+        acc.setdefault(name, []).append(ms_)
+    plan.set_timing(False)
+    out["adjoint_stage_ms"] = {k: sum(v) / len(v) for k, v in acc.items()}
     del plan, f, q, pt
     out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
     if not args.no_fp64 and args.precision != "f64":

@@ -72,10 +72,16 @@ typedef enum {
  *  K         interpolation length (Section 3.1 step (ii)); 2*c*K must be an
  *            integer between 2 and 64 (the number of taps per node).
  *  alpha     Kaiser-Bessel width (Section 3.2), pi < alpha < pi*(2c-1);
- *            0 selects 0.98*pi*(2c-1) ("slightly smaller than pi(2c-1)",
- *            Section 5).
+ *            0 selects 0.98*pi*(2c-1), just below the upper limit, as the
+ *            numerical experiments of Section 5 do.
  *  precision a pat_precision.
  * Every FFT length (nx[0], nx[1], nz, c*nt) must factor into primes <= 23.
+ * A line of c*nt (and of nz) complex values must fit one workgroup's LDS:
+ * c*nt <= 8192 in float, 4096 in double; larger sizes make pat_plan_create
+ * return PAT_ERR_UNSUPPORTED.  The operators that spread (reconstruct
+ * adjoint, forward model, nufft1_lines) also keep per-node lists of a depth
+ * line in LDS, which bounds nz to about 1700 in float and 880 in double;
+ * beyond that those calls return PAT_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t ndim;

@@ -28,6 +28,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "launch.h"
 #include "pat_internal.h"
@@ -242,9 +244,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>
   }
 }
 
+// tw: the L roots exp(-2 pi i k / L) of this transform (in LDS in every kernel)
 template <typename T, bool P2, bool BF>
-__device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw_all, int nb, int bs, int es) {
-  const cx<T>* tw = tw_all + d.tw;
+__device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw, int nb, int bs, int es) {
   const int L = d.L;
   int Li = L;
   for (int s = 0; s < d.nst; ++s) {
@@ -319,7 +321,7 @@ struct StageArgs {
   const Inst* inst[kMaxBatch];
   const void* in[kMaxBatch];
   void* out[kMaxBatch];
-  uint32_t* counter;  // persistent queue, or nullptr: item = blockIdx.x
+  uint32_t* counter;  // persistent queue, or nullptr: items blockIdx.x + i gridDim.x
   int32_t len_nz;     // transverse passes: lines have nz (else nt) samples
   int32_t mode;       // FFT direction (0 forward, 1 inverse) / interp, spread mode
   int32_t pair_ok;    // pc holds every instance's mirrored tap-pair polynomials
@@ -327,6 +329,13 @@ struct StageArgs {
   // then odd part (x^1, x^3, ...) of tap p's polynomial, in the compute type
   alignas(8) uint32_t pc[kPolyWords];
 };
+
+// Copies the L roots of one FFT length from the instance table into LDS.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cx<T>* dst, const Inst& I, const FftDesc& d) {
+  const cx<T>* src = static_cast<const cx<T>*>(I.tw) + d.tw;
+  for (int e = threadIdx.x; e < d.L; e += kBlock) dst[e] = src[e];
+}
 
 // ---------------------------------------------------------------------------
 // Kaiser-Bessel interpolation kernel.  With s = sqrt(K^2 - u^2), |u| <= K,
@@ -703,7 +712,7 @@ __device__ __forceinline__ int next_item(const StageArgs& a, int iter, int* s_it
     __syncthreads();
     item = *s_item;
   } else {
-    item = iter == 0 ? (int)blockIdx.x : a.total;
+    item = (int)blockIdx.x + iter * (int)gridDim.x;
   }
   return __builtin_amdgcn_readfirstlane(item);
 }
@@ -714,12 +723,18 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
   return i;
 }
 
+// Loop over the work items of this workgroup.  I is the item's instance, li
+// its index within the instance; new_inst_ is true when the instance differs
+// from the previous item's (per-instance LDS tables are then reloaded).
 #define PAT_FOR_EACH_ITEM(a)                                              \
   __shared__ int s_item_;                                                 \
+  int prev_inst_ = -1;                                                    \
   for (int iter_ = 0;; ++iter_) {                                         \
     const int item_ = next_item(a, iter_, &s_item_);                      \
     if (item_ >= (a).total) break;                                        \
     const int inst_ = __builtin_amdgcn_readfirstlane(find_inst(a, item_)); \
+    const bool new_inst_ = inst_ != prev_inst_;                           \
+    prev_inst_ = inst_;                                                   \
     const Inst& I = *(a).inst[inst_];                                     \
     const int li = item_ - (a).off[inst_];
 
@@ -739,8 +754,10 @@ extern __shared__ __align__(16) unsigned char pat_smem[];
 
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.n1;
+  if (new_inst_) load_twiddles(tw, I, I.f1);
   const int len = a.len_nz ? I.nz : I.nt;  // even
   const int tb = I.tb;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
@@ -761,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   cx<T>* out0 = out + (size_t)x2 * len + t0;
   for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
@@ -785,8 +802,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
 
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.n2;
+  if (new_inst_) load_twiddles(tw, I, I.f2);
   const int len = a.len_nz ? I.nz : I.nt;
   const int tb = I.tb;
   const int ntile = (len + tb - 1) / tb;
@@ -805,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f2, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f2, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f2.perm;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
     int k, b;
@@ -825,8 +844,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 // taking the real part of the full inverse DFT does.
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.n1;
+  if (new_inst_) load_twiddles(tw, I, I.f1);
   const int len = a.len_nz ? I.nz : I.nt;
   const int tb = I.tb;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
@@ -862,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f1, static_cast<const cx<T>*>(I.tw), tb, 1, tb);
+  fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   T* out0 = out + (size_t)x2 * len + t0;
   for (int e = threadIdx.x; e < L * tb; e += kBlock) {
@@ -882,8 +903,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 // DFT of length nz along each line, in place.
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.nz;
+  if (new_inst_) load_twiddles(tw, I, I.fz);
   const int L = I.nz;
   const int line0 = li * I.lpw_z;
   const int nl = min(I.lpw_z, I.lines - line0);
@@ -897,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, true>(buf, I.fz, static_cast<const cx<T>*>(I.tw), nl, L, 1);
+  fft_lds<T, P2, true>(buf, I.fz, tw, nl, L, 1);
   const int32_t* perm = I.perm + I.fz.perm;
   for (int e = threadIdx.x; e < nl * L; e += kBlock) {
     int b, j;
@@ -929,14 +952,16 @@ __device__ __forceinline__ void load_deconv_pad(const Inst& I, const cx<T>* g, i
 
 template <typename T, typename G, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.m;
+  if (new_inst_) load_twiddles(tw, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
   load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, buf);
   __syncthreads();
-  fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
+  fft_lds<T, P2, true>(buf, I.fm, tw, nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
   G* grid = static_cast<G*>(a.out[inst_]);
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
@@ -950,10 +975,10 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
 // transpose of a2 on LDS grids (natural order, conjugated on entry by the
 // caller): X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
 template <typename T, bool P2>
-__device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int nl, cx<T>* x) {
+__device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int nl, cx<T>* x, const cx<T>* twm) {
   const int m = I.m, nt = I.nt;
   const T* sn = static_cast<const T*>(I.sn);
-  fft_lds<T, P2, true>(buf, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
+  fft_lds<T, P2, true>(buf, I.fm, twm, nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
   for (int e = threadIdx.x; e < nl * nt; e += kBlock) {
     int b, n;
@@ -966,8 +991,10 @@ __device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int 
 
 template <typename T, typename G, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
-  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   PAT_FOR_EACH_ITEM(a)
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = tw + I.m;
+  if (new_inst_) load_twiddles(tw, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
@@ -976,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
       nl * m, [&](int e) { return cconj(GridIO<T, G>::ld(grid, (size_t)line0 * m + e)); },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  ifft_pick_deconv<T, P2>(I, buf, nl, static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt);
+  ifft_pick_deconv<T, P2>(I, buf, nl, static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt, tw);
   PAT_END_ITEM
 }
 
@@ -1047,11 +1074,15 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   const int H = pairs ? TAPS - 1 : 0;
   const int ls = m + H;
   const int sp = m > nz ? m : nz;
+  // (twiddles stay in global memory here: an LDS copy costs this kernel a
+  // resident workgroup per CU and the strided reads conflict on banks)
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
   cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
   cx<T>* gn = gp + lpw * sp;                         // grid in natural order, with halo
   load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, gp);
   __syncthreads();
-  fft_lds<T, P2, true>(gp, I.fm, static_cast<const cx<T>*>(I.tw), nl, m, 1);
+  fft_lds<T, P2, true>(gp, I.fm, twm, nl, m, 1);
   const int32_t* permm = I.perm + I.fm.perm;
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
     int b, j;
@@ -1070,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
     interp_lines<T, 0, false, P2>(I, a, gn, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
   }
   __syncthreads();
-  fft_lds<T, P2, true>(fz, I.fz, static_cast<const cx<T>*>(I.tw), nl, nz, 1);
+  fft_lds<T, P2, true>(fz, I.fz, twz, nl, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
@@ -1087,13 +1118,15 @@ template <typename T, bool P2, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz, nt = I.nt;
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;  // (global, as in k_line_nufft2)
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
   cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // m
   cx<T>* q = grid + m;                                // nz
   const SpreadLds<T> L = SpreadLds<T>::carve(q + nz, nz, I.taps);
   const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
   copy_batched<2>(nz, [&](int e) { return in[e]; }, [&](int e, cx<T> v) { q[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, true>(q, I.fz, static_cast<const cx<T>*>(I.tw), 1, nz, 1);
+  fft_lds<T, P2, true>(q, I.fz, twz, 1, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
   auto fget = [&](int l) { return q[permz[l]]; };
   auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
@@ -1103,7 +1136,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
     spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put);
   }
   __syncthreads();
-  ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt);
+  ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt, twm);
   PAT_END_ITEM
 }
 
@@ -1130,6 +1163,21 @@ int num_cu() {
   return g_num_cu;
 }
 
+// Workgroups of kBlock threads that one CU holds at once for this kernel and
+// LDS size (cached: the query is not free and the answer never changes).
+int resident_blocks(const void* kernel, size_t shmem) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kernel, shmem});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, shmem) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  cache[{kernel, shmem}] = per_cu;
+  return per_cu;
+}
+
 template <typename K>
 hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st, StageTimer* tm) {
   if (a.total <= 0) return hipSuccess;
@@ -1138,11 +1186,10 @@ hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStr
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
   }
-  int grid = a.total;
-  if (a.counter) {
-    const int cap = 8 * num_cu();
-    grid = a.total < cap ? a.total : cap;
-  }
+  // one workgroup per item; with a work counter, a persistent grid of as many
+  // workgroups as fit on the device at once
+  const int cap = a.counter ? resident_blocks(reinterpret_cast<const void*>(kernel), shmem) * num_cu() : a.total;
+  const int grid = a.total < cap ? a.total : cap;
   if (tm) tm->begin(name, st);
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), shmem, st, a);
   hipError_t e = hipGetLastError();

@@ -66,10 +66,11 @@ struct Inst {
 // element, rs: per real).  The kernels carve their LDS exactly as described
 // here; the host plan uses the same functions for its capacity checks and the
 // launchers for the dynamic LDS request.
-inline size_t lds_tile_x1(const Inst& I, size_t cs) { return (size_t)I.n1 * I.tb * cs; }
-inline size_t lds_tile_x2(const Inst& I, size_t cs) { return (size_t)I.n2 * I.tb * cs; }
-inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.lpw_z * I.nz * cs; }
-inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.lpw_m * I.m * cs; }
+// (FFT kernels start with the twiddle table of each length they transform)
+inline size_t lds_tile_x1(const Inst& I, size_t cs) { return (size_t)I.n1 * (I.tb + 1) * cs; }
+inline size_t lds_tile_x2(const Inst& I, size_t cs) { return (size_t)I.n2 * (I.tb + 1) * cs; }
+inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.nz * (I.lpw_z + 1) * cs; }
+inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.m * (I.lpw_m + 1) * cs; }
 // interp: lpw_i grid lines of m entries plus a halo of taps - 1
 inline size_t lds_interp(const Inst& I, size_t cs) { return (size_t)I.lpw_i * ((size_t)I.m + I.taps) * cs; }
 // spreading lists: per-node value, zero-padded tap-weight row (taps + 6

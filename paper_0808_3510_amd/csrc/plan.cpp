@@ -2,6 +2,7 @@
 // (deconvolution factors, FFT twiddles and index maps, node/weight constants).
 #include "plan.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -263,13 +264,15 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.h1 = n1 / 2 + 1;
   I.lines = I.h1 * n2;
   I.taps = taps;
-  int tb = prec == PAT_F64 ? 16 : 32;
-  const int lmax = n1 > n2 ? n1 : n2;
-  while (tb > 1 && (size_t)lmax * tb * cs > 65536) tb /= 2;
-  I.tb = tb;
+  I.tb = prec == PAT_F64 ? 8 : 16;
+  while (I.tb > 1 && std::max(lds_tile_x1(I, cs), lds_tile_x2(I, cs)) > 65536) I.tb /= 2;
   I.pow2 = is_pow2(n1) && is_pow2(n2) && is_pow2(m) && is_pow2(g.nz);
   I.lpw_m = clampi(2048 / m, 1, 16);
   I.lpw_z = clampi(2048 / g.nz, 1, 16);
+  if (lds_line_z(I, cs) > kLdsMax) {
+    msg << "nz = " << g.nz << " exceeds the LDS line capacity for this precision";
+    return fail(PAT_ERR_UNSUPPORTED);
+  }
   I.lpw_i = clampi(kBlock / g.nz, 1, 8);
   while (I.lpw_i > 1 && lds_interp(I, cs) > 65536) --I.lpw_i;
   I.lpw_f = clampi(2048 / m, 1, 16);
@@ -393,6 +396,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   p->g = g;
   p->prec = prec;
   p->fusable = I.fused != 0;
+  p->spread_ok = lds_spread(I, complex_bytes(prec)) <= kLdsMax;
   p->inst = I;
   p->off_desc = 0;
   p->off_tw = off_tw;

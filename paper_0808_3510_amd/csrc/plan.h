@@ -18,6 +18,7 @@ struct pat_plan {
   void* table_dev = nullptr;
   bool uploaded = false;
   bool fusable = false;    // the fused line kernels fit this geometry and precision
+  bool spread_ok = false;  // the spreading lists of a depth line fit in LDS (R^T, A)
   bool timing = false;
   void* timer = nullptr;   // owned by the ABI layer
 };

@@ -43,6 +43,7 @@ def test_valid_plan_sizes():
     (dict(alpha=3.0), 1), (dict(alpha=20.0), 1), (dict(precision=7), 1),
     (dict(n1=58), 2),            # 29 is not a supported FFT radix
     (dict(n1=8192, n2=2), 2), (dict(nt=16384), 2), (dict(K=32.0, c=2.0), 1),
+    (dict(nz=8192, precision="f64"), 2),   # a double depth line pair exceeds LDS
 ])
 def test_invalid_geometry_is_rejected(kw, status):
     with pytest.raises(pat.PatError) as ei:
