@@ -1007,6 +1007,102 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
   PAT_END_ITEM
 }
 
+// 16-byte chunks of a stored grid line: EPC elements per chunk, unpacked to
+// compute precision and stored to LDS (dst is 16-byte aligned).
+template <typename T, typename G>
+struct GridChunk;
+template <>
+struct GridChunk<float, cx<float>> {
+  static constexpr int EPC = 2;
+  static __device__ __forceinline__ void put(uint4 v, cx<float>* dst) { *reinterpret_cast<uint4*>(dst) = v; }
+};
+template <>
+struct GridChunk<double, cx<double>> {
+  static constexpr int EPC = 1;
+  static __device__ __forceinline__ void put(uint4 v, cx<double>* dst) { *reinterpret_cast<uint4*>(dst) = v; }
+};
+template <>
+struct GridChunk<float, bf2> {
+  static constexpr int EPC = 4;
+  static __device__ __forceinline__ void put(uint4 v, cx<float>* dst) {
+    float4 lo, hi;
+    lo.x = __uint_as_float(v.x << 16);
+    lo.y = __uint_as_float(v.x & 0xffff0000u);
+    lo.z = __uint_as_float(v.y << 16);
+    lo.w = __uint_as_float(v.y & 0xffff0000u);
+    hi.x = __uint_as_float(v.z << 16);
+    hi.y = __uint_as_float(v.z & 0xffff0000u);
+    hi.z = __uint_as_float(v.w << 16);
+    hi.w = __uint_as_float(v.w & 0xffff0000u);
+    reinterpret_cast<float4*>(dst)[0] = lo;
+    reinterpret_cast<float4*>(dst)[1] = hi;
+  }
+};
+
+// a3 alone on the stored grid of one instance, streamed.  A persistent
+// workgroup walks line groups (lpw_i lines) with stride gridDim.x; the next
+// group's grid is loaded into registers (16-byte loads) before the current
+// group is interpolated, so each workgroup keeps its memory requests in
+// flight while it computes.  Two LDS buffers of lpw_i lines (each with a
+// halo of TAPS - 1 and a stride rounded to 16 bytes) alternate; one barrier
+// per group suffices because a buffer is refilled only after the following
+// group's barrier, which every thread reaches after its last read of it.
+template <typename T, typename G, int TAPS, bool P2, int NPRE>
+__global__ __launch_bounds__(kBlock) void k_line_interp_stream(StageArgs a) {
+  using C = GridChunk<T, G>;
+  constexpr int EPC = C::EPC;
+  constexpr int H = TAPS - 1;
+  constexpr int Q = 16 / (int)sizeof(cx<T>) > 0 ? 16 / (int)sizeof(cx<T>) : 1;
+  const Inst& I = *a.inst[0];
+  const int m = I.m, nz = I.nz, lpw = I.lpw_i, lines = I.lines;
+  const int ls = (m + H + Q - 1) / Q * Q;
+  const int ngroups = a.total;
+  const G* grid = static_cast<const G*>(a.in[0]);
+  cx<T>* out = static_cast<cx<T>*>(a.out[0]);
+  cx<T>* bufs = reinterpret_cast<cx<T>*>(pat_smem);
+  __shared__ double s_ak[2][16];
+  uint4 pre[NPRE];
+  auto fetch = [&](int g) {
+    const int line0 = g * lpw;
+    const int nch = min(lpw, lines - line0) * m / EPC;
+    const uint4* src = reinterpret_cast<const uint4*>(grid + (size_t)line0 * m);
+#pragma unroll
+    for (int u = 0; u < NPRE; ++u) {
+      const int c = (int)threadIdx.x + u * kBlock;
+      if (c < nch) pre[u] = src[c];
+    }
+  };
+  int g = blockIdx.x;
+  if (g >= ngroups) return;
+  fetch(g);
+  for (int k = 0; g < ngroups; g += gridDim.x, ++k) {
+    cx<T>* buf = bufs + (k & 1) * lpw * ls;
+    const int line0 = g * lpw;
+    const int nl = min(lpw, lines - line0);
+    const int nch = nl * m / EPC;
+#pragma unroll
+    for (int u = 0; u < NPRE; ++u) {
+      const int c = (int)threadIdx.x + u * kBlock;
+      if (c < nch) {
+        int b, j;
+        divmod<P2>(c * EPC, m, &b, &j);
+        cx<T>* dst = buf + b * ls + j;
+        C::put(pre[u], dst);
+        if (j < H) {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e)
+            if (j + e < H) dst[m + e] = dst[e];
+        }
+      }
+    }
+    if ((int)threadIdx.x < nl) s_ak[k & 1][threadIdx.x] = line_ak(I, line0 + (int)threadIdx.x);
+    if (g + (int)gridDim.x < ngroups) fetch(g + (int)gridDim.x);
+    __syncthreads();
+    cx<T>* o = out + (size_t)line0 * nz;
+    interp_lines<T, TAPS, true, P2>(I, a, buf, ls, s_ak[k & 1], nl, a.mode, [&](int e, cx<T> v) { o[e] = v; });
+  }
+}
+
 // a3 alone: grid lines from memory, weighted node values to memory.
 template <typename T, typename G, int TAPS, bool P2>
 __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
@@ -1197,6 +1293,26 @@ hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStr
   return e;
 }
 
+// A persistent grid (as many workgroups as fit at once, at most one per item)
+// for kernels that stride over their items themselves.
+template <typename K>
+hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st,
+                             StageTimer* tm) {
+  if (a.total <= 0) return hipSuccess;
+  if (shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+  }
+  const int cap = resident_blocks(reinterpret_cast<const void*>(kernel), shmem) * num_cu();
+  const int grid = a.total < cap ? a.total : cap;
+  if (tm) tm->begin(name, st);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), shmem, st, a);
+  hipError_t e = hipGetLastError();
+  if (tm) tm->end(st);
+  return e;
+}
+
 enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LINE };
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -1309,6 +1425,20 @@ struct Runner {
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LI, true, mode, in, out);
+    if constexpr (TAPS > 0) {
+      // one instance with the paired taps: the streamed kernel, with enough
+      // 16-byte registers per thread for a line group
+      constexpr int EPC = GridChunk<T, G>::EPC;
+      const Inst& I = h[0];
+      const int per = (I.lpw_i * I.m / EPC + kBlock - 1) / kBlock;
+      if (n == 1 && a.pair_ok && I.m % EPC == 0 && per <= 8 && !counters) {
+        const size_t shm = lds_interp_stream(I, cs);
+        if (per <= 1) return launch_persistent(k_line_interp_stream<T, G, TAPS, P2, 1>, "interp", a, shm, st, tm);
+        if (per <= 2) return launch_persistent(k_line_interp_stream<T, G, TAPS, P2, 2>, "interp", a, shm, st, tm);
+        if (per <= 4) return launch_persistent(k_line_interp_stream<T, G, TAPS, P2, 4>, "interp", a, shm, st, tm);
+        return launch_persistent(k_line_interp_stream<T, G, TAPS, P2, 8>, "interp", a, shm, st, tm);
+      }
+    }
     return launch(k_line_interp<T, G, TAPS, P2>, "interp", a,
                   max_over([](const Inst& I) { return lds_interp(I, cs); }), st, tm);
   }
