@@ -384,13 +384,40 @@ __device__ __forceinline__ NodePos node_pos(double nu, double c, double ck) {
   return p;
 }
 
-// exp(-i pi nu), argument reduced in double to [-1, 1].
+// exp(-i pi nu), argument reduced in double to r in [-1, 1].  Double: the
+// library sincospi.  Float: r = s + q/2 with |s| <= 1/4 and q = rint(2r);
+// sin and cos of pi s from polynomials in s^2 fitted by least squares
+// (gen_sincospi.py; largest error below 1e-7 when evaluated in float),
+// rotated by q quarter turns.
 template <typename T>
 __device__ __forceinline__ cx<T> phase_mpi(double nu) {
   const double r = nu - 2.0 * rint(0.5 * nu);
   T s, c;
   m_sincospi((T)r, &s, &c);
   return mk(c, -s);
+}
+template <>
+__device__ __forceinline__ cx<float> phase_mpi<float>(double nu) {
+  const float r = (float)(nu - 2.0 * rint(0.5 * nu));
+  const float q = rintf(2.0f * r);
+  const float s = fmaf(-0.5f, q, r);
+  const float u = s * s;
+  float ps = fmaf(u, -0.5890768766403198f, 2.549767017364502f);
+  ps = fmaf(u, ps, -5.167707920074463f);
+  ps = fmaf(u, ps, 3.1415927410125732f);
+  const float sn = s * ps;
+  float pc = fmaf(u, 0.23132924735546112f, -1.335044503211975f);
+  pc = fmaf(u, pc, 4.058707237243652f);
+  pc = fmaf(u, pc, -4.934802055358887f);
+  const float cs = fmaf(u, pc, 1.0f);
+  // sin(pi (s + q/2)), cos(pi (s + q/2)) for q mod 4 = 0, 1, 2, 3:
+  // (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn)
+  const int qi = (int)q & 3;
+  float sv = (qi & 1) ? cs : sn;
+  float cv = (qi & 1) ? sn : cs;
+  if (qi == 1 || qi == 2) cv = -cv;
+  if (qi >= 2) sv = -sv;
+  return mk(cv, -sv);
 }
 
 // nu+ = sqrt(A) and 1/nu in double from a float estimate and one Newton step
@@ -446,18 +473,22 @@ struct Node {
   T x;
   cx<T> ph;
 };
-template <typename T>
+template <typename T, bool P2>
 __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, double inv_m) {
   const double xc = I.c * nu;
   const double f = floor(xc - I.ck);
   Node<T> nd;
   nd.x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
-  // (f + 1) mod m without an integer division
-  const double j1 = f + 1.0;
-  int j0 = (int)(j1 - (double)m * floor(j1 * inv_m));
-  if (j0 >= m) j0 -= m;
-  if (j0 < 0) j0 += m;
-  nd.j0 = j0;
+  if constexpr (P2) {
+    nd.j0 = ((int)f + 1) & (m - 1);
+  } else {
+    // (f + 1) mod m without an integer division
+    const double j1 = f + 1.0;
+    int j0 = (int)(j1 - (double)m * floor(j1 * inv_m));
+    if (j0 >= m) j0 -= m;
+    if (j0 < 0) j0 += m;
+    nd.j0 = j0;
+  }
   nd.ph = phase_mpi<T>(nu);
   return nd;
 }
@@ -465,10 +496,10 @@ __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, do
 // exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m].  With PAIRS the
 // grid line carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
 // U[j0 .. j0 + TAPS - 1] without wrapping.
-template <typename T, int TAPS, bool PAIRS>
+template <typename T, int TAPS, bool PAIRS, bool P2>
 __device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double inv_m, double nu, const Inst& I,
                                              const StageArgs& a) {
-  const Node<T> nd = make_node<T>(nu, I, m, inv_m);
+  const Node<T> nd = make_node<T, P2>(nu, I, m, inv_m);
   cx<T> acc = mk(T(0), T(0));
   if constexpr (PAIRS) {
     T w[TAPS];
@@ -505,10 +536,15 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
 // l = 0), mean of the nodes -+nu+ on l = -nz/2.  mode 1 (A^T): mean of the
 // nodes +-nu+ for every l, no weight.  put(e, value) receives output
 // e = b*nz + l_index.  akl[b] holds line b's |K_x|^2 term.
+// Every lane evaluates one node per output in mode 0: the lane of l = 0,
+// whose weight is 0, evaluates the +nu+ half of the Nyquist plane and the
+// lane of l = -nz/2 the -nu+ half; the halves meet in LDS after a barrier
+// (uniform in the workgroup), so no wave runs a second evaluation path.
 template <typename T, int TAPS, bool PAIRS, bool P2, typename Put>
 __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls,
                                              const double* akl, int nl, int mode, Put put) {
-  const int m = I.m, nz = I.nz;
+  __shared__ cx<T> s_nyq[2 * 16];
+  const int m = I.m, nz = I.nz, half = nz / 2;
   const double wsc = I.wcoef * I.scale;
   const double inv_m = 1.0 / (double)m;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
@@ -516,28 +552,31 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
     divmod<P2>(e, nz, &b, &il);
     const cx<T>* Ub = U + b * ls;
     const double Ak = akl[b];
-    const int l = 2 * il < nz ? il : il - nz;
-    const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
-    cx<T> v;
     if (mode == 0) {
-      if (l == 0) {
-        v = mk(T(0), T(0));
-      } else {
-        const double w = wsc * (double)(l < 0 ? -l : l) * rcp_nt(nup);
-        if (2 * l == -nz) {
-          v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, -nup, I, a),
-                   interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, nup, I, a));
-          v = cscl(v, T(0.5 * w));
-        } else {
-          v = cscl(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, l > 0 ? nup : -nup, I, a), T(w));
-        }
-      }
+      const bool nyq = il == 0 || il == half;
+      const int la = nyq ? half : (il < half ? il : nz - il);
+      const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
+      const double w = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
+      const cx<T> v = cscl(interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, il < half ? nup : -nup, I, a), T(w));
+      if (nyq)
+        s_nyq[2 * b + (il == 0 ? 1 : 0)] = v;
+      else
+        put(e, v);
     } else {
-      v = cadd(interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, nup, I, a),
-               interp_eval<T, TAPS, PAIRS>(Ub, m, inv_m, -nup, I, a));
-      v = cscl(v, T(0.5 * I.scale));
+      const int l = il < half ? il : il - nz;
+      const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
+      cx<T> v = cadd(interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, nup, I, a),
+                     interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, -nup, I, a));
+      put(e, cscl(v, T(0.5 * I.scale)));
     }
-    put(e, v);
+  }
+  if (mode == 0) {
+    __syncthreads();
+    if ((int)threadIdx.x < nl) {
+      const int b = threadIdx.x;
+      put(b * nz, mk(T(0), T(0)));
+      put(b * nz + half, cadd(s_nyq[2 * b], s_nyq[2 * b + 1]));
+    }
   }
 }
 
