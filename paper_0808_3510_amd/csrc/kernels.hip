@@ -464,14 +464,13 @@ __device__ __forceinline__ T tap_weight(const Inst& I, int t, T x) {
   return kb_phi<T>((delta - T(t)) * T(1.0 / I.c), T(I.K), T(I.alpha));
 }
 
-// Node quantities on the oversampled grid for nu (time-bin units):
-// first tap j0 = floor(c nu - cK) + 1 reduced mod m, polynomial offset
-// x = 2 (c nu - j0 - cK) + 1 in (-1, 1], and exp(-i pi nu).
+// Node position on the oversampled grid for nu (time-bin units): first tap
+// j0 = floor(c nu - cK) + 1 reduced mod m, polynomial offset
+// x = 2 (c nu - j0 - cK) + 1 in (-1, 1].
 template <typename T>
 struct Node {
   int j0;
   T x;
-  cx<T> ph;
 };
 template <typename T, bool P2>
 __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, double inv_m) {
@@ -489,16 +488,15 @@ __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, do
     if (j0 < 0) j0 += m;
     nd.j0 = j0;
   }
-  nd.ph = phase_mpi<T>(nu);
   return nd;
 }
 
-// exp(-i pi nu) sum_t phi((delta - t)/c) U[(j0 + t) mod m].  With PAIRS the
-// grid line carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
+// sum_t phi((delta - t)/c) U[(j0 + t) mod m] at nu.  With PAIRS the grid line
+// carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
 // U[j0 .. j0 + TAPS - 1] without wrapping.
 template <typename T, int TAPS, bool PAIRS, bool P2>
-__device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double inv_m, double nu, const Inst& I,
-                                             const StageArgs& a) {
+__device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, double nu, const Inst& I,
+                                         const StageArgs& a) {
   const Node<T> nd = make_node<T, P2>(nu, I, m, inv_m);
   cx<T> acc = mk(T(0), T(0));
   if constexpr (PAIRS) {
@@ -521,7 +519,17 @@ __device__ __forceinline__ cx<T> interp_eval(const cx<T>* U, int m, double inv_m
       if (++jm == m) jm = 0;
     }
   }
-  return cmul(acc, nd.ph);
+  return acc;
+}
+
+// The type-2 values at the node pair +nup and -nup:
+// exp(-+i pi nup) sum_t phi(...) U[...]; the two phases are conjugate.
+template <typename T, int TAPS, bool PAIRS, bool P2>
+__device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m, double nup, const Inst& I,
+                                            const StageArgs& a, cx<T>* vp, cx<T>* vn) {
+  const cx<T> ph = phase_mpi<T>(nup);
+  *vp = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, nup, I, a), ph);
+  *vn = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, -nup, I, a), cconj(ph));
 }
 
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
@@ -532,50 +540,47 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
 }
 
 // a3 over a group of nl lines whose grids sit in LDS in natural order at
-// U + b*ls.  mode 0 (R): node sign(l) nu+, weight wcoef |l| / nu+ (0 at
-// l = 0), mean of the nodes -+nu+ on l = -nz/2.  mode 1 (A^T): mean of the
-// nodes +-nu+ for every l, no weight.  put(e, value) receives output
-// e = b*nz + l_index.  akl[b] holds line b's |K_x|^2 term.
-// Every lane evaluates one node per output in mode 0: the lane of l = 0,
-// whose weight is 0, evaluates the +nu+ half of the Nyquist plane and the
-// lane of l = -nz/2 the -nu+ half; the halves meet in LDS after a barrier
-// (uniform in the workgroup), so no wave runs a second evaluation path.
+// U + b*ls, by node pairs: the nodes of l and -l are +nu+ and -nu+ with
+// nu+ = sqrt(Ak + b l^2), one lane per pair, sharing nu+, the weight and the
+// phase.  mode 0 (R): pairs |l| = 1 .. nz/2; output l gets
+// wcoef |l| / nu+ times the value at sign(l) nu+; the Nyquist plane
+// l = -nz/2 gets the mean of both, and l = 0 gets 0 (weight 0).  mode 1
+// (A^T): pairs |l| = 0 .. nz/2; outputs l and -l both get the mean of the two
+// values, no weight.  put(e, value) receives output e = b*nz + l_index.
+// akl[b] holds line b's |K_x|^2 term.
 template <typename T, int TAPS, bool PAIRS, bool P2, typename Put>
 __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls,
                                              const double* akl, int nl, int mode, Put put) {
-  __shared__ cx<T> s_nyq[2 * 16];
   const int m = I.m, nz = I.nz, half = nz / 2;
   const double wsc = I.wcoef * I.scale;
   const double inv_m = 1.0 / (double)m;
-  for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
-    int b, il;
-    divmod<P2>(e, nz, &b, &il);
-    const cx<T>* Ub = U + b * ls;
-    const double Ak = akl[b];
+  const int per = mode == 0 ? half : half + 1;
+  for (int e = threadIdx.x; e < nl * per; e += kBlock) {
+    int b, p;
     if (mode == 0) {
-      const bool nyq = il == 0 || il == half;
-      const int la = nyq ? half : (il < half ? il : nz - il);
-      const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
-      const double w = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
-      const cx<T> v = cscl(interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, il < half ? nup : -nup, I, a), T(w));
-      if (nyq)
-        s_nyq[2 * b + (il == 0 ? 1 : 0)] = v;
-      else
-        put(e, v);
+      divmod<P2>(e, half, &b, &p);
     } else {
-      const int l = il < half ? il : il - nz;
-      const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
-      cx<T> v = cadd(interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, nup, I, a),
-                     interp_eval<T, TAPS, PAIRS, P2>(Ub, m, inv_m, -nup, I, a));
-      put(e, cscl(v, T(0.5 * I.scale)));
+      b = e / per;
+      p = e - b * per;
     }
-  }
-  if (mode == 0) {
-    __syncthreads();
-    if ((int)threadIdx.x < nl) {
-      const int b = threadIdx.x;
-      put(b * nz, mk(T(0), T(0)));
-      put(b * nz + half, cadd(s_nyq[2 * b], s_nyq[2 * b + 1]));
+    const int la = mode == 0 ? p + 1 : p;
+    const double nup = sqrt_nt(akl[b] + I.b * (double)la * (double)la);
+    cx<T> vp, vn;
+    interp_pair<T, TAPS, PAIRS, P2>(U + b * ls, m, inv_m, nup, I, a, &vp, &vn);
+    const int o = b * nz;
+    if (mode == 0) {
+      const double w = wsc * (double)la * rcp_nt(nup);
+      if (la < half) {
+        put(o + la, cscl(vp, T(w)));
+        put(o + nz - la, cscl(vn, T(w)));
+      } else {
+        put(o + half, cscl(cadd(vp, vn), T(0.5 * w)));
+        put(o, mk(T(0), T(0)));
+      }
+    } else {
+      const cx<T> v = cscl(cadd(vp, vn), T(0.5 * I.scale));
+      put(o + la, v);
+      if (la > 0 && la < half) put(o + nz - la, v);
     }
   }
 }

@@ -273,7 +273,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
     msg << "nz = " << g.nz << " exceeds the LDS line capacity for this precision";
     return fail(PAT_ERR_UNSUPPORTED);
   }
-  I.lpw_i = clampi(kBlock / g.nz, 1, 8);
+  I.lpw_i = clampi(2 * kBlock / g.nz, 1, 16);  // one lane per node pair
   while (I.lpw_i > 1 && lds_interp(I, cs) > 65536) --I.lpw_i;
   I.lpw_f = clampi(2048 / m, 1, 16);
   while (I.lpw_f > 1 && lds_fused2(I, cs) > 65536) --I.lpw_f;
