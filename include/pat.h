@@ -80,7 +80,7 @@ typedef enum {
  * c*nt <= 8192 in float, 4096 in double; larger sizes make pat_plan_create
  * return PAT_ERR_UNSUPPORTED.  The operators that spread (reconstruct
  * adjoint, forward model, nufft1_lines) also keep per-node lists of a depth
- * line in LDS, which bounds nz to about 1700 in float and 880 in double;
+ * line in LDS, which bounds nz to about 1800 in float and 900 in double;
  * beyond that those calls return PAT_ERR_UNSUPPORTED.
  */
 typedef struct {

@@ -586,136 +586,139 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 }
 
 // Type-1 spreading of one line, the transpose of interp_lines' sum.  The
-// line's nodes are listed in increasing order (monotone in l by construction);
-// for each node the taps contributions w_t * value (t < taps) are formed
-// once into LDS, with its first tap j0 (unreduced).  A start table maps each
-// first-tap index v (relative to the smallest) to the first node with
-// j0 >= v.  Grid cell j then gathers, for each periodic image and each tap t,
-// the nodes whose first tap is j - t: a contiguous node range read from two
-// neighbouring start entries, summed in node order.  No atomics and no
-// dependent loads; the result is deterministic.
-//   mode 0 (R^T): nodes sign(l) nu+ for l = -nz/2 .. nz/2-1 plus +nu+(nz/2);
-//     value conj(W exp(-i pi nu) scale) Qhat_l, halved on the Nyquist plane,
-//     whose value feeds both -nu+ and +nu+.
-//   mode 1 (A): nodes -nu+(nz/2) .. -nu+(0), +nu+(0) .. +nu+(nz/2); value
+// line's nodes are listed in increasing order; one lane forms the pair
+// -nu+, +nu+ of |l| (shared root, phase and coefficient): its first taps j0
+// (unreduced), values, and tap weights (node-major rows with kPad zeros on
+// both sides and an odd stride, so consecutive nodes' rows start on
+// different LDS banks).  Cell j then gathers, for each periodic image and
+// each tap t, the nodes whose first tap is j - t: a contiguous node range
+// whose ends come from the closed form of the node positions, corrected
+// against the stored j0 (so the ranges are exact).  Summation is in node
+// order: no atomics, deterministic.
+//   mode 0 (R^T): nodes -nu+(nz/2 .. 1), +nu+(1 .. nz/2); value
+//     conj(W exp(-i pi nu) scale) Qhat_l with l = sign(nu)|l|, except that
+//     both Nyquist nodes take Qhat_{-nz/2} with half the weight (l = 0 has
+//     weight 0 and is left out).
+//   mode 1 (A): nodes -nu+(nz/2 .. 0), +nu+(0 .. nz/2); value
 //     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
 // fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
 template <typename T>
 struct SpreadLds {
-  // Cells gathered per thread, and the zero padding on each side of a node's
-  // weight row that lets a block of kCells cells read kCells weights of any
-  // node in range without bounds tests.
+  // a thread gathers kCells consecutive cells; kPad zeros on both sides of a
+  // weight row let it read kCells weights of any node in range without tests
   static constexpr int kCells = 4;
   static constexpr int kPad = kCells - 1;
-  static __host__ __device__ constexpr int row(int taps) { return ((taps + 2 * kPad + 3) / 4) * 4; }
+  static __host__ __device__ constexpr int row(int taps) { return (taps + 2 * kPad) | 1; }
   cx<T>* val;  // [node] value
   T* wts;      // [node][row] tap weights, tap t at kPad + t
-  int* j0s;
-  int* start;
+  int* j0s;    // [node] first tap, unreduced
   static __device__ __forceinline__ SpreadLds carve(void* base, int nz, int taps) {
     SpreadLds s;
     const int nn = nz + 2;
     s.val = static_cast<cx<T>*>(base);
     s.wts = reinterpret_cast<T*>(s.val + nn);
     s.j0s = reinterpret_cast<int*>(s.wts + nn * row(taps));
-    s.start = s.j0s + nn;
     return s;
   }
 };
 
+// First tap and weight row of node i at nu.
+template <typename T, int TAPS, bool PAIRS>
+__device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, double nu, SpreadLds<T> L, int i,
+                                            int taps, int rw) {
+  constexpr int P = SpreadLds<T>::kPad;
+  const double xc = I.c * nu;
+  const double f = floor(xc - I.ck);
+  const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
+  L.j0s[i] = (int)f + 1;
+  T* wi = L.wts + i * rw;
+#pragma unroll
+  for (int t = 0; t < P; ++t) wi[t] = T(0);
+  for (int t = P + taps; t < rw; ++t) wi[t] = T(0);
+  if constexpr (PAIRS) {
+    T w[TAPS];
+    tap_weights_pairs<T, TAPS>(a, x, w);
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) wi[P + t] = w[t];
+  } else {
+    for (int t = 0; t < taps; ++t) wi[P + t] = tap_weight<T>(I, t, x);
+  }
+}
+
 template <typename T, int TAPS, bool PAIRS, typename Fget, typename Put>
 __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, int line, int mode, SpreadLds<T> L,
                                             Fget fget, Put put) {
-  const int m = I.m, nz = I.nz, taps = PAIRS ? TAPS : I.taps;
-  const int nn = mode == 0 ? nz + 1 : nz + 2;
+  const int m = I.m, nz = I.nz, half = nz / 2, taps = PAIRS ? TAPS : I.taps;
+  const int q0 = mode == 0 ? 1 : 0;  // smallest |l| listed
+  const int nq = half - q0 + 1;      // |l| values, one node pair each
+  const int nn = 2 * nq;             // nodes
   const double Ak = line_ak(I, line);
-  const int half = nz / 2;
   const double wsc = I.wcoef * I.scale;
-  for (int i = threadIdx.x; i < nn; i += kBlock) {
-    double nu, cf;
-    cx<T> q;
+  const int rw = SpreadLds<T>::row(taps);
+  for (int p = threadIdx.x; p < nq; p += kBlock) {
+    const int la = q0 + p;
+    const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
+    cx<T> qp, qm;
+    double cf;
     if (mode == 0) {
-      const int l = i < nz ? i - half : half;
-      const double nup = sqrt_nt(Ak + I.b * (double)l * (double)l);
-      const int lm = l < 0 ? l + nz : (l == half ? half : l);
-      q = fget(lm);
-      if (i == nz) {
-        nu = nup;
-        cf = 0.5 * wsc * (double)half * rcp_nt(nup);
-      } else {
-        nu = l > 0 ? nup : (l < 0 ? -nup : 0.0);
-        cf = l == 0 ? 0.0 : wsc * (double)(l < 0 ? -l : l) * rcp_nt(nup);
-        if (l == -half) cf *= 0.5;
-      }
+      const bool nyq = la == half;
+      qp = fget(nyq ? half : la);
+      qm = fget(nyq ? half : nz - la);
+      cf = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
     } else {
-      int mp;
-      double sg;
-      if (i <= half) {
-        mp = half - i;
-        sg = -1.0;
-      } else {
-        mp = i - half - 1;
-        sg = 1.0;
-      }
-      const double nup = sqrt_nt(Ak + I.b * (double)mp * (double)mp);
-      nu = sg * nup;
-      q = fget(mp);
-      if (mp != 0 && mp != half) q = cadd(q, fget(nz - mp));
+      qp = fget(la);
+      if (la != 0 && la != half) qp = cadd(qp, fget(nz - la));
+      qm = qp;
       cf = 0.5 * I.scale;
     }
-    const double xc = I.c * nu;
-    const double f = floor(xc - I.ck);
-    const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
-    L.val[i] = cscl(cmul(q, cconj(phase_mpi<T>(nu))), T(cf));
-    L.j0s[i] = (int)f + 1;
-    constexpr int P = SpreadLds<T>::kPad;
-    const int rw = SpreadLds<T>::row(taps);
-    T* wi = L.wts + i * rw;
-    for (int t = 0; t < P; ++t) wi[t] = T(0);
-    for (int t = P + taps; t < rw; ++t) wi[t] = T(0);
-    if constexpr (PAIRS) {
-      T w[TAPS];
-      tap_weights_pairs<T, TAPS>(a, x, w);
-#pragma unroll
-      for (int t = 0; t < TAPS; ++t) wi[P + t] = w[t];
-    } else {
-      for (int t = 0; t < taps; ++t) wi[P + t] = tap_weight<T>(I, t, x);
-    }
+    // the value at nu is q conj(exp(-i pi nu)) cf; the phases at +-nup are
+    // conjugate
+    const cx<T> ph = phase_mpi<T>(nup);
+    const int ip = nq + p, im = nq - 1 - p;
+    L.val[ip] = cscl(cmul(qp, cconj(ph)), T(cf));
+    L.val[im] = cscl(cmul(qm, ph), T(cf));
+    spread_node<T, TAPS, PAIRS>(I, a, nup, L, ip, taps, rw);
+    spread_node<T, TAPS, PAIRS>(I, a, -nup, L, im, taps, rw);
   }
   __syncthreads();
   const int jlo = L.j0s[0];
-  int span = L.j0s[nn - 1] - jlo + 1;
-  span = span < I.span_max ? span : I.span_max;
-  // start[v] for v in [0, span]: each thread fills a contiguous slice,
-  // locating its first node by binary search and walking forward (the
-  // evanescent band leaves gaps of hundreds of indices without nodes, so a
-  // per-node fill would leave single threads with most of the work)
-  {
-    const int per = (span + kBlock) / kBlock;
-    int v = (int)threadIdx.x * per;
-    const int vstop = v + per < span + 1 ? v + per : span + 1;
-    int lo = 0, hi = nn;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (L.j0s[mid] - jlo < v) lo = mid + 1;
-      else hi = mid;
+  const int span = L.j0s[nn - 1] - jlo + 1;
+  const double inv_c = 1.0 / I.c, inv_b = 1.0 / I.b;
+  // Index of the first node whose first tap is >= jlo + xr.  A node's first
+  // tap is below J exactly when nu < X = (J - 1 + cK) / c; the nodes below X
+  // are counted from nu+(q)^2 = Ak + b q^2, then the count is moved onto the
+  // stored first taps (one or two steps at most in practice).
+  auto first_ge = [&](int xr) -> int {
+    if (xr <= 0) return 0;
+    if (xr >= span) return nn;
+    const int J = jlo + xr;
+    const double X = ((double)(J - 1) + I.ck) * inv_c;
+    const double R = (X * X - Ak) * inv_b;  // bound on q^2
+    const double sq = R > 0.0 ? sqrt_nt(R) : 0.0;
+    int s;
+    if (X > 0.0) {
+      // every -nu+ node, then +nu+(q) for q0 <= q < sqrt(R)
+      int c = R > 0.0 ? (int)ceil(sq) - q0 : 0;
+      c = c < 0 ? 0 : (c > nq ? nq : c);
+      s = nq + c;
+    } else {
+      // -nu+(q) < X  <=>  q^2 > R
+      int c = R >= 0.0 ? (int)floor(sq) - q0 + 1 : 0;
+      c = c < 0 ? 0 : (c > nq ? nq : c);
+      s = nq - c;
     }
-    for (; v < vstop; ++v) {
-      while (lo < nn && L.j0s[lo] - jlo < v) ++lo;
-      L.start[v] = lo;
-    }
-  }
-  __syncthreads();
+    while (s > 0 && L.j0s[s - 1] >= J) --s;
+    while (s < nn && L.j0s[s] < J) ++s;
+    return s;
+  };
   // Each thread owns kCells consecutive cells [j, j + kCells).  For every
   // periodic image (offset v = j + q m - jlo of its first cell, with some
   // cell of the block in [0, span + taps - 1)) the nodes touching the block
   // have first taps in [v - taps + 1, v + kCells - 1]: one contiguous node
-  // range from two start entries.  Node i adds weight (v + c - (j0 - jlo))
-  // times its value to cell c; the padded weight row makes out-of-window taps
-  // read zeros.
+  // range.  Node i adds weight (v + c - (j0 - jlo)) times its value to cell
+  // c; the padded weight row makes out-of-window taps read zeros.
   constexpr int kCells = SpreadLds<T>::kCells;
   constexpr int P = SpreadLds<T>::kPad;
-  const int rw = SpreadLds<T>::row(taps);
   const int vend = span + taps - 1;
   for (int j = kCells * (int)threadIdx.x; j < m; j += kCells * kBlock) {
     cx<T> acc[kCells];
@@ -726,11 +729,8 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
     // the image before may still reach the block's last cells
     if (v - m + kCells - 1 >= 0) v -= m;
     for (; v < vend; v += m) {
-      int lo = v - taps + 1, hi = v + kCells;
-      lo = lo < 0 ? 0 : (lo < span ? lo : span);
-      hi = hi < 0 ? 0 : (hi < span ? hi : span);
-      const int i1 = L.start[hi];
-      for (int i = L.start[lo]; i < i1; ++i) {
+      const int i1 = first_ge(v + kCells);
+      for (int i = first_ge(v - taps + 1); i < i1; ++i) {
         // taps t0 .. t0 + kCells - 1 with t0 = v - (j0 - jlo) in [-P, taps - 1]
         const T* wr = L.wts + i * rw + (P + v - (L.j0s[i] - jlo));
         const cx<T> vv = L.val[i];

@@ -41,7 +41,6 @@ struct Inst {
   int32_t poly;               // 1: per-tap polynomial table valid, 0: direct kernel evaluation
   int32_t lpw_m, lpw_z, lpw_i;  // lines per work item: length-m FFT stages, depth FFT, interp/spread
   int32_t pow2;               // every FFT length is a power of two
-  int32_t span_max;           // bound on the range of first-tap indices of one line's nodes
   int32_t lpw_f;              // lines per work item of the fused line kernels
   int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
   double c, K, alpha;
@@ -81,12 +80,12 @@ inline size_t lds_interp_stream(const Inst& I, size_t cs) {
   return 2 * (size_t)I.lpw_i * ls * cs;
 }
 // spreading lists: per-node value, zero-padded tap-weight row (taps + 6
-// entries rounded up to a multiple of 4), first tap; start table
-inline size_t lds_spread_lists(int nz, int taps, int span_max, size_t cs) {
-  const size_t row = (size_t)((taps + 6 + 3) / 4) * 4;
-  return ((size_t)nz + 2) * (cs + row * (cs / 2) + sizeof(int32_t)) + ((size_t)span_max + 2) * sizeof(int32_t);
+// entries, made odd), first tap; nz + 2 nodes at most
+inline size_t lds_spread_lists(int nz, int taps, size_t cs) {
+  const size_t row = (size_t)((taps + 6) | 1);
+  return ((size_t)nz + 2) * (cs + row * (cs / 2) + sizeof(int32_t));
 }
-inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, I.span_max, cs); }
+inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, cs); }
 // fused type-2 line kernel: lpw_f lines of max(m, nz) (FFT scratch, then the
 // depth line) and lpw_f grid lines of m + taps (natural order with halo)
 inline size_t lds_fused2(const Inst& I, size_t cs) {

@@ -287,11 +287,6 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.b = (tv / (g.nz * g.dz)) * (tv / (g.nz * g.dz));
   I.wcoef = 2.0 * g.vs * (g.dt / g.dz) * std::sqrt(I.b);
   I.scale = 1.0 / (kPi * g.c * (double)n1 * (double)n2 * (double)g.nz);
-  {
-    const double h1v = n1 / 2, h2v = n2 / 2, hz = g.nz / 2;
-    const double numax = std::sqrt(I.a1 * h1v * h1v + I.a2 * h2v * h2v + I.b * hz * hz);
-    I.span_max = (int32_t)std::ceil(2.0 * g.c * numax) + 4;
-  }
 
   // table layout
   size_t off = align256(sizeof(Inst));
