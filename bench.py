@@ -172,6 +172,76 @@ def cpu_baseline(p_np, g, f_gpu, budget_s, np):
     }
 
 
+KERNEL_OF_STAGE = {
+    # library stage name -> kernel symbol prefix in the profiler's output
+    "nufft_fused": "void pat::k_line_nufft2<",
+    "nufft_adjoint_fused": "void pat::k_line_nufft1<",
+    "dft_x1": "void pat::k_tr_x1_r2c<",
+    "dft_x2": "void pat::k_tr_x2<",
+    "idft_x1_c2r": "void pat::k_tr_c2r_k1<",
+}
+
+
+def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision):
+    """HBM bytes per launch of each stage from two rocprofv3 --pmc runs of
+    `bench.py --calibrate-copy copy_bytes` (FETCH_SIZE, then WRITE_SIZE; both
+    in KiB per dispatch).  Each counter is scaled by what it reads for the
+    plain copy of copy_bytes that the run starts with (fetch: the copy's
+    source; write: the fill that creates it), and the result is stored in
+    profiles/traffic.json with the hash of the kernel sources it belongs to."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (r["Kernel_Name"], int(r["Grid_Size"]), r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+                acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        by_name = {}
+        for (name, grid, _), v in acc.items():
+            by_name.setdefault((name, grid), []).append(v)
+        return by_name
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def largest(d, pred):
+        # the largest copy/fill dispatch (the calibration one)
+        best = None
+        for (name, _), vals in d.items():
+            if pred(name):
+                v = max(vals)
+                best = v if best is None or v > best else best
+        return best
+
+    kib = copy_bytes / 1024.0
+    f_copy = largest(fetch, lambda n: "copy" in n.lower() or "elementwise" in n.lower())
+    w_fill = largest(write, lambda n: "fill" in n.lower() or "elementwise" in n.lower())
+    f_scale, w_scale = kib / f_copy, kib / w_fill
+    out = {"kernel_source": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale, "bytes_per_launch": {}, "raw_kib_per_launch": {}}
+    # one entry per stage and launch size (a kernel serves several stages and
+    # both R and R^T); the key carries the grid size when a stage has several
+    for stage, prefix in KERNEL_OF_STAGE.items():
+        grids = sorted({g for (n, g) in fetch if n.startswith(prefix)})
+        for g in grids:
+            fv = [v for (n, gg), vs in fetch.items() if n.startswith(prefix) and gg == g for v in vs]
+            wv = [v for (n, gg), vs in write.items() if n.startswith(prefix) and gg == g for v in vs]
+            if not fv or not wv:
+                continue
+            f_avg, w_avg = sum(fv) / len(fv), sum(wv) / len(wv)
+            key = f"{stage}:{workload}:{precision}" + (f"[grid={g}]" if len(grids) > 1 else "")
+            out["raw_kib_per_launch"][key] = {"fetch": f_avg, "write": w_avg, "dispatches": [len(fv), len(wv)],
+                                              "grid_threads": g}
+            out["bytes_per_launch"][key] = 1024.0 * (f_avg * f_scale + w_avg * w_scale)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,7 +254,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_BYTES"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files (no GPU work)")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], int(args.traffic_from[2]), args.workload,
+                              args.precision)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)

@@ -586,9 +586,9 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 }
 
 // Type-1 spreading of one line, the transpose of interp_lines' sum.  The
-// line's nodes are listed in increasing order; one lane forms the pair
-// -nu+, +nu+ of |l| (shared root, phase and coefficient): its first taps j0
-// (unreduced), values, and tap weights (node-major rows with kPad zeros on
+// line's nodes are listed in increasing order (the pairs -nu+, +nu+ of each
+// |l|), one lane per node: first tap j0 (unreduced), value, and tap weights
+// (node-major rows with kPad zeros on
 // both sides and an odd stride, so consecutive nodes' rows start on
 // different LDS banks).  Cell j then gathers, for each periodic image and
 // each tap t, the nodes whose first tap is j - t: a contiguous node range
@@ -601,7 +601,8 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 //     weight 0 and is left out).
 //   mode 1 (A): nodes -nu+(nz/2 .. 0), +nu+(0 .. nz/2); value
 //     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
-// fget(l_index) reads the depth spectrum, put(j, value) receives cell j.
+// fget(l_index) reads the depth spectrum, put(j, value) receives cell j and
+// put4(j, values) the four cells j .. j + 3 (j a multiple of 4).
 template <typename T>
 struct SpreadLds {
   // a thread gathers kCells consecutive cells; kPad zeros on both sides of a
@@ -645,9 +646,9 @@ __device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, d
   }
 }
 
-template <typename T, int TAPS, bool PAIRS, typename Fget, typename Put>
+template <typename T, int TAPS, bool PAIRS, typename Fget, typename Put, typename Put4>
 __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, int line, int mode, SpreadLds<T> L,
-                                            Fget fget, Put put) {
+                                            Fget fget, Put put, Put4 put4) {
   const int m = I.m, nz = I.nz, half = nz / 2, taps = PAIRS ? TAPS : I.taps;
   const int q0 = mode == 0 ? 1 : 0;  // smallest |l| listed
   const int nq = half - q0 + 1;      // |l| values, one node pair each
@@ -655,30 +656,27 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
   const double Ak = line_ak(I, line);
   const double wsc = I.wcoef * I.scale;
   const int rw = SpreadLds<T>::row(taps);
-  for (int p = threadIdx.x; p < nq; p += kBlock) {
-    const int la = q0 + p;
+  for (int i = threadIdx.x; i < nn; i += kBlock) {
+    // node i: +nu+(q0 + i - nq) for i >= nq, else -nu+(q0 + nq - 1 - i)
+    const bool pos = i >= nq;
+    const int la = q0 + (pos ? i - nq : nq - 1 - i);
     const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
-    cx<T> qp, qm;
+    cx<T> q;
     double cf;
     if (mode == 0) {
       const bool nyq = la == half;
-      qp = fget(nyq ? half : la);
-      qm = fget(nyq ? half : nz - la);
+      q = fget(nyq ? half : (pos ? la : nz - la));
       cf = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
     } else {
-      qp = fget(la);
-      if (la != 0 && la != half) qp = cadd(qp, fget(nz - la));
-      qm = qp;
+      q = fget(la);
+      if (la != 0 && la != half) q = cadd(q, fget(nz - la));
       cf = 0.5 * I.scale;
     }
     // the value at nu is q conj(exp(-i pi nu)) cf; the phases at +-nup are
     // conjugate
     const cx<T> ph = phase_mpi<T>(nup);
-    const int ip = nq + p, im = nq - 1 - p;
-    L.val[ip] = cscl(cmul(qp, cconj(ph)), T(cf));
-    L.val[im] = cscl(cmul(qm, ph), T(cf));
-    spread_node<T, TAPS, PAIRS>(I, a, nup, L, ip, taps, rw);
-    spread_node<T, TAPS, PAIRS>(I, a, -nup, L, im, taps, rw);
+    L.val[i] = cscl(cmul(q, pos ? cconj(ph) : ph), T(cf));
+    spread_node<T, TAPS, PAIRS>(I, a, pos ? nup : -nup, L, i, taps, rw);
   }
   __syncthreads();
   const int jlo = L.j0s[0];
@@ -742,9 +740,13 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
         }
       }
     }
+    if (j + kCells <= m) {
+      put4(j, acc);
+    } else {
 #pragma unroll
-    for (int c = 0; c < kCells; ++c)
-      if (j + c < m) put(j + c, acc[c]);
+      for (int c = 0; c < kCells; ++c)
+        if (j + c < m) put(j + c, acc[c]);
+    }
   }
 }
 
@@ -1051,6 +1053,33 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
   PAT_END_ITEM
 }
 
+// Four consecutive grid cells to memory (p 16-byte aligned for the vector
+// forms; bf16 falls back to single cells otherwise).
+template <typename T, typename G>
+__device__ __forceinline__ void grid_store4(G* p, const cx<T>* v) {
+  if constexpr (sizeof(G) == 8 && sizeof(T) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    q[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+  } else if constexpr (sizeof(G) == 16) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q[c] = make_double2(v[c].x, v[c].y);
+  } else {
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+      uint4 u;
+      u.x = (uint32_t)f2bf(v[0].x) | ((uint32_t)f2bf(v[0].y) << 16);
+      u.y = (uint32_t)f2bf(v[1].x) | ((uint32_t)f2bf(v[1].y) << 16);
+      u.z = (uint32_t)f2bf(v[2].x) | ((uint32_t)f2bf(v[2].y) << 16);
+      u.w = (uint32_t)f2bf(v[3].x) | ((uint32_t)f2bf(v[3].y) << 16);
+      *reinterpret_cast<uint4*>(p) = u;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) GridIO<T, G>::st(p, c, v[c]);
+    }
+  }
+}
+
 // 16-byte chunks of a stored grid line: EPC elements per chunk, unpacked to
 // compute precision and stored to LDS (dst is 16-byte aligned).
 template <typename T, typename G>
@@ -1190,10 +1219,11 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
   const size_t row = (size_t)li * I.m;
   auto fget = [&](int l) { return F[l]; };
   auto put = [&](int j, cx<T> v) { GridIO<T, G>::st(grid, row + j, v); };
+  auto put4 = [&](int j, const cx<T>* v) { grid_store4<T, G>(grid + row + j, v); };
   if (TAPS > 0 && a.pair_ok) {
-    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put);
+    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put, put4);
   } else {
-    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put);
+    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put, put4);
   }
   PAT_END_ITEM
 }
@@ -1270,10 +1300,14 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   const int32_t* permz = I.perm + I.fz.perm;
   auto fget = [&](int l) { return q[permz[l]]; };
   auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
+  auto put4 = [&](int j, const cx<T>* v) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) grid[j + c] = cconj(v[c]);
+  };
   if (TAPS > 0 && a.pair_ok) {
-    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put);
+    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put, put4);
   } else {
-    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put);
+    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put, put4);
   }
   __syncthreads();
   ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt, twm);
