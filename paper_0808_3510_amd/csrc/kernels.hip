@@ -234,8 +234,25 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = p[r * st];
       dft_pow2<T, R>(v);
+      // one table twiddle w = exp(-2 pi i j / Li) per butterfly; its powers
+      // w^2 .. w^(R-1) by a product tree at most three products deep (the
+      // last stage, sub = 1, has j = 0 and no twiddles)
+      if (sub > 1) {
+      cx<T> w[R];
+      w[1] = tw[j * tws];
+      if constexpr (R >= 4) {
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+      }
+      if constexpr (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+      }
 #pragma unroll
-      for (int d = 1; d < R; ++d) v[d] = cmul(v[d], tw[j * d * tws]);
+      for (int d = 1; d < R; ++d) v[d] = cmul(v[d], w[d]);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) p[r * st] = v[r];
     } else {
@@ -274,6 +291,68 @@ __device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ 
     __syncthreads();
     Li /= R;
   }
+}
+
+// Natural (frequency) index of the in-place DIF output at position pos: the
+// digits of pos, most significant first, are those of k, least significant
+// first (radices of the stages in order); power-of-two radices.
+__device__ __forceinline__ int dif_natural_p2(const FftDesc& d, int pos) {
+  int k = 0, sh = 0, lspan = __builtin_ctz((unsigned)d.L);
+  for (int s = 0; s < d.nst; ++s) {
+    const int lr = __builtin_ctz((unsigned)d.rad[s]);
+    lspan -= lr;
+    k += (pos >> lspan) << sh;
+    pos &= (1 << lspan) - 1;
+    sh += lr;
+  }
+  return k;
+}
+
+// The last stage (sub = 1, no twiddles) of a power-of-two DIF transform,
+// handing each butterfly's R outputs (positions blk*R + r) to
+// sink(b, blk, v) instead of writing them back.
+template <typename T, int R, bool BF, typename Sink>
+__device__ __forceinline__ void fft_last_stage_p2(const cx<T>* buf, int L, int nb, int bs, int es, Sink sink) {
+  const int nbf = L / R;
+  const int lnbf = __builtin_ctz((unsigned)nbf), lnb = __builtin_ctz((unsigned)nb);
+  for (int id = threadIdx.x; id < nbf * nb; id += kBlock) {
+    int b, blk;
+    if constexpr (BF) {
+      blk = id & (nbf - 1);
+      b = id >> lnbf;
+    } else {
+      b = id & (nb - 1);
+      blk = id >> lnb;
+    }
+    const cx<T>* p = buf + b * bs + blk * R * es;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = p[r * es];
+    dft_pow2<T, R>(v);
+    sink(b, blk, v);
+  }
+}
+
+// fft_lds for power-of-two lengths whose result goes to sink(b, blk, v[R])
+// from the last stage (see fft_last_stage_p2) rather than back into buf.
+template <typename T, bool BF, typename Sink>
+__device__ void fft_lds_p2_sink(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw, int nb, int bs, int es,
+                                Sink sink) {
+  const int L = d.L;
+  int Li = L;
+  for (int s = 0; s + 1 < d.nst; ++s) {
+    const int R = d.rad[s];
+    if (R == 8) fft_stage<T, 8, true, BF>(buf, Li, L, tw, nb, bs, es);
+    else if (R == 4) fft_stage<T, 4, true, BF>(buf, Li, L, tw, nb, bs, es);
+    else fft_stage<T, 2, true, BF>(buf, Li, L, tw, nb, bs, es);
+    __syncthreads();
+    Li /= R;
+  }
+  const int R = d.rad[d.nst - 1];
+  if (R == 8) fft_last_stage_p2<T, 8, BF>(buf, L, nb, bs, es, sink);
+  else if (R == 4) fft_last_stage_p2<T, 4, BF>(buf, L, nb, bs, es, sink);
+  else fft_last_stage_p2<T, 2, BF>(buf, L, nb, bs, es, sink);
+  __syncthreads();
 }
 
 // quotient and remainder by a length that is a power of two in the P2 path
@@ -790,13 +869,50 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
 
 extern __shared__ __align__(16) unsigned char pat_smem[];
 
+// Two neighbouring complex values (or four reals) as one 16-byte access for
+// float; double values are 16 bytes each already.
+// NT marks data that no later stage reads back (the operator's input and
+// output arrays): it streams past the caches, which keep the intermediate
+// arrays that the next stage reads.
+template <typename T, bool NT = false>
+__device__ __forceinline__ void ld_pair(const cx<T>* p, cx<T>* a, cx<T>* b) {
+  if constexpr (sizeof(T) == 4) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f v;
+    if constexpr (NT)
+      v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+    else
+      v = *reinterpret_cast<const v4f*>(p);
+    *a = mk(v.x, v.y);
+    *b = mk(v.z, v.w);
+  } else {
+    *a = p[0];
+    *b = p[1];
+  }
+}
+template <typename T, bool NT = false>
+__device__ __forceinline__ void st_pair(cx<T>* p, cx<T> a, cx<T> b) {
+  if constexpr (sizeof(T) == 4) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = {a.x, a.y, b.x, b.y};
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p));
+    else
+      *reinterpret_cast<v4f*>(p) = v;
+  } else {
+    p[0] = a;
+    p[1] = b;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Transverse passes.  Tiles of consecutive samples (t or z, the contiguous
 // axis) by the full transform length; lanes run along the samples, so global
 // accesses are contiguous runs.  The real passes pack two neighbouring real
 // samples into one complex column (real and imaginary part) and separate the
 // two transforms afterwards, so a tile of tb complex columns covers 2 tb
-// samples.
+// samples.  Global accesses move two columns (16 bytes in float) per lane
+// where the alignment allows it.
 
 template <typename T, bool P2>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
@@ -814,15 +930,34 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   const int L = I.n1;
   const size_t rstride = (size_t)I.n2 * len;
   const T* in0 = in + (size_t)x2 * len + t0;
-  copy_batched<8>(
-      L * tb,
-      [&](int e) {
-        int x, b;
-        divmod<true>(e, tb, &x, &b);
-        // samples t0 + 2b (real part) and t0 + 2b + 1 (imaginary part); len is even
-        return t0 + 2 * b < len ? *reinterpret_cast<const cx<T>*>(in0 + x * rstride + 2 * b) : mk(T(0), T(0));
-      },
-      [&](int e, cx<T> v) { buf[e] = v; });
+  if (len % 4 == 0 && tb % 2 == 0) {
+    // column pairs: samples t0 + 4c .. t0 + 4c + 3 (len is a multiple of 4)
+    const int hb = tb / 2;
+    copy_batched<4>(
+        L * hb,
+        [&](int e) {
+          int x, c;
+          divmod<true>(e, hb, &x, &c);
+          cx<T> u[2] = {mk(T(0), T(0)), mk(T(0), T(0))};
+          if (t0 + 4 * c < len)
+            ld_pair<T, true>(reinterpret_cast<const cx<T>*>(in0 + x * rstride + 4 * c), &u[0], &u[1]);
+          return cx<cx<T>>{u[0], u[1]};
+        },
+        [&](int e, cx<cx<T>> v) {
+          buf[2 * e] = v.x;
+          buf[2 * e + 1] = v.y;
+        });
+  } else {
+    copy_batched<8>(
+        L * tb,
+        [&](int e) {
+          int x, b;
+          divmod<true>(e, tb, &x, &b);
+          // samples t0 + 2b (real part) and t0 + 2b + 1 (imaginary part); len is even
+          return t0 + 2 * b < len ? *reinterpret_cast<const cx<T>*>(in0 + x * rstride + 2 * b) : mk(T(0), T(0));
+        },
+        [&](int e, cx<T> v) { buf[e] = v; });
+  }
   __syncthreads();
   fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
@@ -839,9 +974,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
     const cx<T> pa = cscl(cadd(z, zn), h);
     const cx<T> d = csub(z, zn);
     const cx<T> pb = mk(h * d.y, -h * d.x);
-    cx<T>* o = out0 + (size_t)k * rstride + 2 * b;
-    o[0] = pa;
-    o[1] = pb;
+    st_pair(out0 + (size_t)k * rstride + 2 * b, pa, pb);
   }
   PAT_END_ITEM
 }
@@ -860,24 +993,54 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   cx<T>* io = static_cast<cx<T>*>(a.out[inst_]) + (size_t)k1 * I.n2 * len + t0;
   const int L = I.n2;
   const bool inv = a.mode != 0;
-  copy_batched<8>(
-      L * tb,
-      [&](int e) {
-        int x, b;
-        divmod<true>(e, tb, &x, &b);
-        const cx<T> v = t0 + b < len ? io[(size_t)x * len + b] : mk(T(0), T(0));
-        return inv ? cconj(v) : v;
-      },
-      [&](int e, cx<T> v) { buf[e] = v; });
+  // column pairs b, b + 1 when tb is even (b even; len is even, so both or
+  // neither exist), single columns otherwise
+  const int hb = tb / 2;
+  if (tb % 2 == 0) {
+    copy_batched<4>(
+        L * hb,
+        [&](int e) {
+          int x, c;
+          divmod<true>(e, hb, &x, &c);
+          cx<T> u[2] = {mk(T(0), T(0)), mk(T(0), T(0))};
+          if (t0 + 2 * c < len) ld_pair(io + (size_t)x * len + 2 * c, &u[0], &u[1]);
+          return cx<cx<T>>{inv ? cconj(u[0]) : u[0], inv ? cconj(u[1]) : u[1]};
+        },
+        [&](int e, cx<cx<T>> v) {
+          buf[2 * e] = v.x;
+          buf[2 * e + 1] = v.y;
+        });
+  } else {
+    copy_batched<8>(
+        L * tb,
+        [&](int e) {
+          int x, b;
+          divmod<true>(e, tb, &x, &b);
+          const cx<T> v = t0 + b < len ? io[(size_t)x * len + b] : mk(T(0), T(0));
+          return inv ? cconj(v) : v;
+        },
+        [&](int e, cx<T> v) { buf[e] = v; });
+  }
   __syncthreads();
   fft_lds<T, P2, false>(buf, I.f2, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f2.perm;
-  for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    int k, b;
-    divmod<true>(e, tb, &k, &b);
-    if (t0 + b < len) {
-      const cx<T> v = buf[perm[k] * tb + b];
-      io[(size_t)k * len + b] = inv ? cconj(v) : v;
+  if (tb % 2 == 0) {
+    for (int e = threadIdx.x; e < L * hb; e += kBlock) {
+      int k, c;
+      divmod<true>(e, hb, &k, &c);
+      if (t0 + 2 * c < len) {
+        const cx<T>* s = buf + perm[k] * tb + 2 * c;
+        st_pair(io + (size_t)k * len + 2 * c, inv ? cconj(s[0]) : s[0], inv ? cconj(s[1]) : s[1]);
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < L * tb; e += kBlock) {
+      int k, b;
+      divmod<true>(e, tb, &k, &b);
+      if (t0 + b < len) {
+        const cx<T> v = buf[perm[k] * tb + b];
+        io[(size_t)k * len + b] = inv ? cconj(v) : v;
+      }
     }
   }
   PAT_END_ITEM
@@ -912,11 +1075,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
         divmod<true>(e, tb, &k, &b);
         const int src = k <= half ? k : L - k;
         cx<T> xa = mk(T(0), T(0)), xb = mk(T(0), T(0));
-        if (t0 + 2 * b < len) {
-          const cx<T>* p = in0 + (size_t)src * rstride + 2 * b;
-          xa = p[0];
-          xb = p[1];
-        }
+        if (t0 + 2 * b < len) ld_pair(in0 + (size_t)src * rstride + 2 * b, &xa, &xb);
         if (k == 0 || k == half) {
           xa.y = T(0);
           xb.y = T(0);
@@ -932,12 +1091,26 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   T* out0 = out + (size_t)x2 * len + t0;
-  for (int e = threadIdx.x; e < L * tb; e += kBlock) {
-    int x, b;
-    divmod<true>(e, tb, &x, &b);
-    if (t0 + 2 * b < len) {
-      const cx<T> y = buf[perm[x] * tb + b];  // conj of x_a + i x_b
-      *reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 2 * b) = mk(y.x, -y.y);
+  if (len % 4 == 0 && tb % 2 == 0) {
+    // four samples per lane (len is a multiple of 4)
+    const int hb = tb / 2;
+    for (int e = threadIdx.x; e < L * hb; e += kBlock) {
+      int x, c;
+      divmod<true>(e, hb, &x, &c);
+      if (t0 + 4 * c < len) {
+        const cx<T>* y = buf + perm[x] * tb + 2 * c;  // conj of x_a + i x_b
+        st_pair<T, true>(reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 4 * c), mk(y[0].x, -y[0].y),
+                         mk(y[1].x, -y[1].y));
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < L * tb; e += kBlock) {
+      int x, b;
+      divmod<true>(e, tb, &x, &b);
+      if (t0 + 2 * b < len) {
+        const cx<T> y = buf[perm[x] * tb + b];  // conj of x_a + i x_b
+        *reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 2 * b) = mk(y.x, -y.y);
+      }
     }
   }
   PAT_END_ITEM
@@ -1251,18 +1424,34 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
   cx<T>* gn = gp + lpw * sp;                         // grid in natural order, with halo
   load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, gp);
-  __syncthreads();
-  fft_lds<T, P2, true>(gp, I.fm, twm, nl, m, 1);
-  const int32_t* permm = I.perm + I.fm.perm;
-  for (int e = threadIdx.x; e < nl * m; e += kBlock) {
-    int b, j;
-    divmod<P2>(e, m, &b, &j);
-    const cx<T> v = gp[b * m + permm[j]];
-    gn[b * ls + j] = v;
-    if (j < H) gn[b * ls + m + j] = v;
-  }
   if (threadIdx.x < nl) s_ak[threadIdx.x] = line_ak(I, line0 + threadIdx.x);
   __syncthreads();
+  if constexpr (P2) {
+    // the last FFT stage writes the grid in natural order (with its halo)
+    const int step = m / I.fm.rad[I.fm.nst - 1];  // weight of the last digit in k
+    fft_lds_p2_sink<T, true>(gp, I.fm, twm, nl, m, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* g = gn + b * ls;
+      const int k0 = dif_natural_p2(I.fm, blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int kk = k0 + r * step;
+        g[kk] = v[r];
+        if (kk < H) g[m + kk] = v[r];
+      }
+    });
+  } else {
+    fft_lds<T, P2, true>(gp, I.fm, twm, nl, m, 1);
+    const int32_t* permm = I.perm + I.fm.perm;
+    for (int e = threadIdx.x; e < nl * m; e += kBlock) {
+      int b, j;
+      divmod<P2>(e, m, &b, &j);
+      const cx<T> v = gp[b * m + permm[j]];
+      gn[b * ls + j] = v;
+      if (j < H) gn[b * ls + m + j] = v;
+    }
+    __syncthreads();
+  }
   cx<T>* fz = gp;  // the permuted grid is no longer needed
   if (pairs) {
     interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, gn, ls, s_ak, nl, a.mode,

@@ -285,10 +285,18 @@ def test_config5_batched_vs_oracle(config5):
 
 
 def test_config5_batched_equals_single_calls(config5):
+    """The persistent batched launch against one call per instance.  A launch
+    over mixed sizes runs the general-radix kernel build, a single call on a
+    power-of-two instance the specialised one; the compiler may fuse multiply
+    and add differently in the two, so the results agree to float rounding,
+    not bit for bit."""
     cases, plans, ps, outs = config5
     for plan, p, f in zip(plans, ps, outs):
         single = plan.reconstruct(p).cpu().numpy()
-        assert np.array_equal(single, f)
+        assert relerr(f.astype(np.float64), single.astype(np.float64)) < 1e-6
+        sizes = (plan.n1, plan.n2, plan.m, plan.nz)
+        if not all(s & (s - 1) == 0 for s in sizes):  # same kernel build: identical
+            assert np.array_equal(single, f)
 
 
 # ---------------------------------------------------------------------------
