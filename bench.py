@@ -9,7 +9,10 @@ of R (all stages a1-a5) on inputs already resident in HBM.
 Prints one JSON line: voxels/s, NUFFT points/s, the FP64-path comparison,
 the roofline of the dominant kernel (per-kernel HIP events recorded by the
 library on the stream its kernels run on), the error against the closed-form
-phantom, and the CPU oracle timed on a bounded sample of the same workload.
+phantom, the adjoint R^T, the stand-alone interpolation and spreading kernels,
+the batched launch over sixteen uneven instances and the 128^3 workload (as
+further line items), and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -116,6 +119,53 @@ def standalone_stages(n, g, steps, torch, dev, pat):
                                     "launches_timed": len(ts)}
         del plan
     return res
+
+
+def batched_and_small(steps, torch, dev, pat, inputs, np):
+    """The other throughput configurations: sixteen uneven instances (plane
+    edges 64 .. 184, time samples twice the edge, depth the edge) in one
+    persistent launch per stage, against one R call per instance; and the
+    128^2 x 256 -> 128^3 workload."""
+    out = {}
+    cases = inputs.batched_case(5000, dtype=np.float32)
+    plans, ps = [], []
+    for p_np, g, _ in cases:
+        plans.append(pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"],
+                              precision="f32", device=dev))
+        ps.append(torch.from_numpy(p_np).to(dev))
+    vox = sum(pl.n1 * pl.n2 * pl.nz for pl in plans)
+    outs, ws = pat.reconstruct_batched(plans, ps)
+    singles = [pl.reconstruct(p) for pl, p in zip(plans, ps)]
+    for _ in range(2):
+        pat.reconstruct_batched(plans, ps, outs, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pat.reconstruct_batched(plans, ps, outs, ws)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for pl, p, f in zip(plans, ps, singles):
+            pl.reconstruct(p, out=f)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / steps * 1e3
+    dev_rel = max(float((torch.linalg.vector_norm(o - s) / torch.linalg.vector_norm(s)).item())
+                  for o, s in zip(outs, singles))
+    out["batched_16_uneven"] = {
+        "edges": [pl.n1 for pl in plans], "total_voxels": vox, "ms_per_launch_set": t_b,
+        "voxels_per_s": vox / (t_b * 1e-3), "sequential_single_calls_ms": t_s,
+        "speedup_over_single_calls": t_s / t_b, "max_relL2_batched_vs_single": dev_rel}
+    del plans, ps, outs, ws, singles
+    p_np, g, _ = inputs.planar_case(128, 8, 1002, noise=1e-3)
+    plan = pat.Plan(128, 128, g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], precision="f32", device=dev)
+    p = torch.from_numpy(p_np).to(dev, torch.float32)
+    f = plan.reconstruct(p)
+    for _ in range(3):
+        plan.reconstruct(p, out=f)
+    ms = time_steps(plan, p, f, steps, torch)
+    out["planar-128x128x256-to-128^3"] = {"ms_per_step": ms, "voxels_per_s": 128 ** 3 / (ms * 1e-3)}
+    return out
 
 
 def cpu_baseline(p_np, g, f_gpu, budget_s, np):
@@ -251,6 +301,7 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16grid"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and 128^3 workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
@@ -364,6 +415,9 @@ def main():
     out["adjoint_stage_ms"] = {k: sum(v) / len(v) for k, v in acc.items()}
     del plan, f, q, pt
     out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
+    if not args.no_extra:
+        print("[bench] batched and 128^3 workloads", file=sys.stderr, flush=True)
+        out["other_workloads"] = batched_and_small(args.steps, torch, dev, pat, inputs, np)
     if not args.no_fp64 and args.precision != "f64":
         print("[bench] timing f64", file=sys.stderr, flush=True)
         plan64, f64, ms64, st64, _ = run_prec("f64")

@@ -166,29 +166,116 @@ __device__ __forceinline__ void dft_pow2(cx<T>* v) {
 // one at a time (roots exp(-2 pi i q / R) read from the L-point table at a
 // workgroup-uniform index) and written back, so no indexed local array is
 // needed.
-template <typename T, int R>
-__device__ __forceinline__ void bfly_prime(cx<T>* p, int st, int j, int tws, const cx<T>* __restrict__ tw,
+template <typename T, int R, typename Ptr>
+__device__ __forceinline__ void bfly_prime(Ptr p, int st, int j, int tws, const cx<T>* __restrict__ tw,
                                            int L) {
-  cx<T> v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = p[r * st];
+  // Odd prime R, outputs d and R - d together: with a_r = x_r + x_{R-r},
+  // b_r = x_r - x_{R-r} (r = 1 .. H) and theta = 2 pi r d / R,
+  //   X_d = x_0 + sum_r a_r cos(theta) - i sum_r b_r sin(theta),
+  //   X_{R-d} = x_0 + sum_r a_r cos(theta) + i sum_r b_r sin(theta).
+  // The roots exp(-2 pi i q / R) come from the length's table: held in
+  // registers for R <= 7, read per use for the larger primes (a loop over d
+  // that is not unrolled keeps their register footprint small).
+  constexpr int H = (R - 1) / 2;
   const int step = L / R;
-  for (int d = 0; d < R; ++d) {
-    cx<T> acc = v[0];
-    int q = 0;
+  const cx<T> x0 = ldx(p);
+  cx<T> av[H + 1], bv[H + 1];
+  cx<T> X0 = x0;
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      q += d;
-      if (q >= R) q -= R;
-      acc = cadd(acc, cmul(v[r], tw[q * step]));
+  for (int r = 1; r <= H; ++r) {
+    const cx<T> u = ldx(p + r * st), v = ldx(p + (R - r) * st);
+    av[r] = cadd(u, v);
+    bv[r] = csub(u, v);
+    X0 = cadd(X0, av[r]);
+  }
+  stx(p, X0);
+  auto emit = [&](int d, cx<T> A, cx<T> B) {
+    cx<T> Xd = mk(A.x + B.y, A.y - B.x), Xm = mk(A.x - B.y, A.y + B.x);
+    if (j) {
+      Xd = cmul(Xd, tw[j * d * tws]);
+      Xm = cmul(Xm, tw[j * (R - d) * tws]);
     }
-    if (d) acc = cmul(acc, tw[j * d * tws]);
-    p[d * st] = acc;
+    stx(p + d * st, Xd);
+    stx(p + (R - d) * st, Xm);
+  };
+  if constexpr (R <= 7) {
+    T cq[H + 1], sq[H + 1];
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      const cx<T> w = tw[q * step];
+      cq[q] = w.x;
+      sq[q] = -w.y;
+    }
+#pragma unroll
+    for (int d = 1; d <= H; ++d) {
+      cx<T> A = x0, B = mk(T(0), T(0));
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        const int q = (r * d) % R;  // compile-time
+        const T c = q <= H ? cq[q] : cq[R - q];
+        const T s = q <= H ? sq[q] : -sq[R - q];
+        A.x += av[r].x * c;
+        A.y += av[r].y * c;
+        B.x += bv[r].x * s;
+        B.y += bv[r].y * s;
+      }
+      emit(d, A, B);
+    }
+  } else {
+#pragma unroll 1
+    for (int d = 1; d <= H; ++d) {
+      cx<T> A = x0, B = mk(T(0), T(0));
+      int q = 0;
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        q += d;
+        if (q >= R) q -= R;
+        const cx<T> w = tw[q * step];  // (cos, -sin) of 2 pi q / R
+        A.x += av[r].x * w.x;
+        A.y += av[r].y * w.x;
+        B.x -= bv[r].x * w.y;
+        B.y -= bv[r].y * w.y;
+      }
+      emit(d, A, B);
+    }
   }
 }
 
-template <typename T, int R, bool P2, bool BF>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>* __restrict__ tw, int nb,
+// Element access through a pointer of any address space (field by field:
+// the implicit copy operations of cx bind to generic-address objects only).
+template <typename P>
+__device__ __forceinline__ auto ldx(P p) {
+  return mk(p->x, p->y);
+}
+template <typename P, typename T>
+__device__ __forceinline__ void stx(P p, cx<T> v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
+// v[d] *= w^d for d = 1 .. R-1 from the one table twiddle w of a butterfly
+// (w = exp(-2 pi i j / Li)); the powers come from a product tree at most
+// three products deep.
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_pow2(cx<T>* v, cx<T> w1) {
+  cx<T> w[R];
+  w[1] = w1;
+  if constexpr (R >= 4) {
+    w[2] = cmul(w[1], w[1]);
+    w[3] = cmul(w[2], w[1]);
+  }
+  if constexpr (R == 8) {
+    w[4] = cmul(w[2], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  }
+#pragma unroll
+  for (int d = 1; d < R; ++d) v[d] = cmul(v[d], w[d]);
+}
+
+template <typename T, int R, bool P2, bool BF, typename Ptr = cx<T>*>
+__device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* __restrict__ tw, int nb,
                                           int bs, int es) {
   const int sub = Li / R;
   const int tws = L / Li;
@@ -227,34 +314,17 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>
       blk = bf / sub;
       j = bf - blk * sub;
     }
-    cx<T>* p = buf + b * bs + (blk * Li + j) * es;
+    Ptr p = buf + b * bs + (blk * Li + j) * es;
     const int st = sub * es;
     if constexpr (R == 2 || R == 4 || R == 8) {
       cx<T> v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = p[r * st];
+      for (int r = 0; r < R; ++r) v[r] = ldx(p + r * st);
       dft_pow2<T, R>(v);
-      // one table twiddle w = exp(-2 pi i j / Li) per butterfly; its powers
-      // w^2 .. w^(R-1) by a product tree at most three products deep (the
-      // last stage, sub = 1, has j = 0 and no twiddles)
-      if (sub > 1) {
-      cx<T> w[R];
-      w[1] = tw[j * tws];
-      if constexpr (R >= 4) {
-        w[2] = cmul(w[1], w[1]);
-        w[3] = cmul(w[2], w[1]);
-      }
-      if constexpr (R == 8) {
-        w[4] = cmul(w[2], w[2]);
-        w[5] = cmul(w[4], w[1]);
-        w[6] = cmul(w[4], w[2]);
-        w[7] = cmul(w[4], w[3]);
-      }
+      // (the last stage, sub = 1, has j = 0 and no twiddles)
+      if (sub > 1) twiddle_pow2<T, R>(v, tw[j * tws]);
 #pragma unroll
-      for (int d = 1; d < R; ++d) v[d] = cmul(v[d], w[d]);
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) p[r * st] = v[r];
+      for (int r = 0; r < R; ++r) stx(p + r * st, v[r]);
     } else {
       bfly_prime<T, R>(p, st, j, tws, tw, L);
     }
@@ -262,8 +332,22 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int Li, int L, const cx<T>
 }
 
 // tw: the L roots exp(-2 pi i k / L) of this transform (in LDS in every kernel)
-template <typename T, bool P2, bool BF>
+// One general-radix stage as a function of its own: called once per stage,
+// it gets its own register allocation instead of sharing one with every
+// other radix of the build.
+template <typename T, int R, bool BF>
+__device__ __noinline__ void fft_stage_fn(cx<T>* buf, int Li, int L, const cx<T>* __restrict__ tw, int nb, int bs,
+                                          int es) {
+  typedef __attribute__((address_space(3))) cx<T>* LdsPtr;
+  fft_stage<T, R, false, BF, LdsPtr>((LdsPtr)buf, Li, L, tw, nb, bs, es);
+}
+
+// RS selects the radix set a kernel build carries: 0 the powers of two (2, 4,
+// 8 with shift arithmetic), 7 the radices up to 7, 23 every radix the plans
+// emit.  A build with fewer radices keeps fewer registers live.
+template <typename T, int RS, bool BF>
 __device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw, int nb, int bs, int es) {
+  constexpr bool P2 = RS == 0;
   const int L = d.L;
   int Li = L;
   for (int s = 0; s < d.nst; ++s) {
@@ -274,17 +358,27 @@ __device__ void fft_lds(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ 
       else fft_stage<T, 2, P2, BF>(buf, Li, L, tw, nb, bs, es);
     } else {
       switch (R) {
-        case 2: fft_stage<T, 2, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 3: fft_stage<T, 3, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 4: fft_stage<T, 4, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 5: fft_stage<T, 5, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 7: fft_stage<T, 7, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 8: fft_stage<T, 8, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 11: fft_stage<T, 11, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 13: fft_stage<T, 13, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 17: fft_stage<T, 17, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 19: fft_stage<T, 19, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
-        case 23: fft_stage<T, 23, P2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 2: fft_stage_fn<T, 2, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 3: fft_stage_fn<T, 3, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 4: fft_stage_fn<T, 4, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 5: fft_stage_fn<T, 5, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 7: fft_stage_fn<T, 7, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 8: fft_stage_fn<T, 8, BF>(buf, Li, L, tw, nb, bs, es); break;
+        case 11:
+          if constexpr (RS >= 11) fft_stage_fn<T, 11, BF>(buf, Li, L, tw, nb, bs, es);
+          break;
+        case 13:
+          if constexpr (RS >= 13) fft_stage_fn<T, 13, BF>(buf, Li, L, tw, nb, bs, es);
+          break;
+        case 17:
+          if constexpr (RS >= 17) fft_stage_fn<T, 17, BF>(buf, Li, L, tw, nb, bs, es);
+          break;
+        case 19:
+          if constexpr (RS >= 19) fft_stage_fn<T, 19, BF>(buf, Li, L, tw, nb, bs, es);
+          break;
+        case 23:
+          if constexpr (RS >= 23) fft_stage_fn<T, 23, BF>(buf, Li, L, tw, nb, bs, es);
+          break;
         default: break;  // the host plan only emits the radices above
       }
     }
@@ -331,6 +425,69 @@ __device__ __forceinline__ void fft_last_stage_p2(const cx<T>* buf, int L, int n
     dft_pow2<T, R>(v);
     sink(b, blk, v);
   }
+}
+
+// The first stage (Li = L) of a power-of-two DIF transform whose inputs come
+// from src(b, pos) rather than buf: butterfly j of transform b takes the
+// positions j + r*sub, and its twiddled outputs go to buf.
+template <typename T, int R, bool BF, typename Src>
+__device__ __forceinline__ void fft_first_stage_p2(cx<T>* buf, int L, const cx<T>* __restrict__ tw, int nb, int bs,
+                                                   int es, Src src) {
+  const int sub = L / R;
+  const int lsub = __builtin_ctz((unsigned)sub), lnb = __builtin_ctz((unsigned)nb);
+  for (int id = threadIdx.x; id < sub * nb; id += kBlock) {
+    int b, j;
+    if constexpr (BF) {
+      j = id & (sub - 1);
+      b = id >> lsub;
+    } else {
+      b = id & (nb - 1);
+      j = id >> lnb;
+    }
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src(b, j + r * sub);
+    dft_pow2<T, R>(v);
+    if (sub > 1) twiddle_pow2<T, R>(v, tw[j]);
+    cx<T>* p = buf + b * bs + j * es;
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r * sub * es] = v[r];
+  }
+}
+
+// fft_lds for power-of-two lengths whose inputs come from src(b, pos) (first
+// stage, see fft_first_stage_p2) and whose result goes to sink(b, blk, v[R])
+// (last stage, see fft_last_stage_p2).
+template <typename T, bool BF, typename Src, typename Sink>
+__device__ void fft_lds_p2_src_sink(cx<T>* buf, const FftDesc& d, const cx<T>* __restrict__ tw, int nb, int bs,
+                                    int es, Src src, Sink sink) {
+  const int L = d.L;
+  if (d.nst == 1) {
+    for (int id = threadIdx.x; id < L * nb; id += kBlock) {
+      const int b = id / L, pos = id - b * L;
+      buf[b * bs + pos * es] = src(b, pos);
+    }
+  } else {
+    const int R0 = d.rad[0];
+    if (R0 == 8) fft_first_stage_p2<T, 8, BF>(buf, L, tw, nb, bs, es, src);
+    else if (R0 == 4) fft_first_stage_p2<T, 4, BF>(buf, L, tw, nb, bs, es, src);
+    else fft_first_stage_p2<T, 2, BF>(buf, L, tw, nb, bs, es, src);
+  }
+  __syncthreads();
+  int Li = d.nst == 1 ? L : L / d.rad[0];
+  for (int s = d.nst == 1 ? 0 : 1; s + 1 < d.nst; ++s) {
+    const int R = d.rad[s];
+    if (R == 8) fft_stage<T, 8, true, BF>(buf, Li, L, tw, nb, bs, es);
+    else if (R == 4) fft_stage<T, 4, true, BF>(buf, Li, L, tw, nb, bs, es);
+    else fft_stage<T, 2, true, BF>(buf, Li, L, tw, nb, bs, es);
+    __syncthreads();
+    Li /= R;
+  }
+  const int R = d.rad[d.nst - 1];
+  if (R == 8) fft_last_stage_p2<T, 8, BF>(buf, L, nb, bs, es, sink);
+  else if (R == 4) fft_last_stage_p2<T, 4, BF>(buf, L, nb, bs, es, sink);
+  else fft_last_stage_p2<T, 2, BF>(buf, L, nb, bs, es, sink);
+  __syncthreads();
 }
 
 // fft_lds for power-of-two lengths whose result goes to sink(b, blk, v[R])
@@ -914,8 +1071,9 @@ __device__ __forceinline__ void st_pair(cx<T>* p, cx<T> a, cx<T> b) {
 // samples.  Global accesses move two columns (16 bytes in float) per lane
 // where the alignment allows it.
 
-template <typename T, bool P2>
+template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n1;
@@ -959,7 +1117,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
         [&](int e, cx<T> v) { buf[e] = v; });
   }
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
+  fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   cx<T>* out0 = out + (size_t)x2 * len + t0;
   for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
@@ -979,8 +1137,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   PAT_END_ITEM
 }
 
-template <typename T, bool P2>
+template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n2;
@@ -1022,7 +1181,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
         [&](int e, cx<T> v) { buf[e] = v; });
   }
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f2, tw, tb, 1, tb);
+  fft_lds<T, RS, false>(buf, I.f2, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f2.perm;
   if (tb % 2 == 0) {
     for (int e = threadIdx.x; e < L * hb; e += kBlock) {
@@ -1051,8 +1210,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 // samples are transformed together: Z = X_a + i X_b inverts to x_a + i x_b.
 // The imaginary parts of the bins 0 and n1/2 are dropped, which is what
 // taking the real part of the full inverse DFT does.
-template <typename T, bool P2>
+template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n1;
@@ -1088,7 +1248,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, false>(buf, I.f1, tw, tb, 1, tb);
+  fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   T* out0 = out + (size_t)x2 * len + t0;
   if (len % 4 == 0 && tb % 2 == 0) {
@@ -1120,8 +1280,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 // Line stages: a group of consecutive frequency lines (k1, k2) per work item.
 
 // DFT of length nz along each line, in place.
-template <typename T, bool P2>
+template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.nz;
@@ -1139,7 +1300,7 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(StageArgs a) {
       },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, true>(buf, I.fz, tw, nl, L, 1);
+  fft_lds<T, RS, true>(buf, I.fz, tw, nl, L, 1);
   const int32_t* perm = I.perm + I.fz.perm;
   for (int e = threadIdx.x; e < nl * L; e += kBlock) {
     int b, j;
@@ -1169,8 +1330,9 @@ __device__ __forceinline__ void load_deconv_pad(const Inst& I, const cx<T>* g, i
       [&](int e, cx<T> v) { buf[e] = v; });
 }
 
-template <typename T, typename G, bool P2>
+template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.m;
@@ -1180,7 +1342,7 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   const int nl = min(I.lpw_m, I.lines - line0);
   load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, buf);
   __syncthreads();
-  fft_lds<T, P2, true>(buf, I.fm, tw, nl, m, 1);
+  fft_lds<T, RS, true>(buf, I.fm, tw, nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
   G* grid = static_cast<G*>(a.out[inst_]);
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
@@ -1193,11 +1355,12 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
 
 // transpose of a2 on LDS grids (natural order, conjugated on entry by the
 // caller): X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
-template <typename T, bool P2>
+template <typename T, int RS>
 __device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int nl, cx<T>* x, const cx<T>* twm) {
+  constexpr bool P2 = RS == 0;
   const int m = I.m, nt = I.nt;
   const T* sn = static_cast<const T*>(I.sn);
-  fft_lds<T, P2, true>(buf, I.fm, twm, nl, m, 1);
+  fft_lds<T, RS, true>(buf, I.fm, twm, nl, m, 1);
   const int32_t* perm = I.perm + I.fm.perm;
   for (int e = threadIdx.x; e < nl * nt; e += kBlock) {
     int b, n;
@@ -1208,8 +1371,9 @@ __device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int 
   }
 }
 
-template <typename T, typename G, bool P2>
+template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.m;
@@ -1222,7 +1386,7 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
       nl * m, [&](int e) { return cconj(GridIO<T, G>::ld(grid, (size_t)line0 * m + e)); },
       [&](int e, cx<T> v) { buf[e] = v; });
   __syncthreads();
-  ifft_pick_deconv<T, P2>(I, buf, nl, static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt, tw);
+  ifft_pick_deconv<T, RS>(I, buf, nl, static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt, tw);
   PAT_END_ITEM
 }
 
@@ -1405,8 +1569,9 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
 // lines, the detector spectrum is deconvolved, padded and transformed in
 // LDS, brought to natural order, interpolated at the line's nodes, and the
 // node values are inverse-transformed over depth before the only store.
-template <typename T, bool P2, int TAPS>
+template <typename T, int RS, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   __shared__ double s_ak[16];
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nt = I.nt, nz = I.nz;
@@ -1423,13 +1588,20 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
   cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
   cx<T>* gn = gp + lpw * sp;                         // grid in natural order, with halo
-  load_deconv_pad<T, P2>(I, static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt, nl, gp);
   if (threadIdx.x < nl) s_ak[threadIdx.x] = line_ak(I, line0 + threadIdx.x);
-  __syncthreads();
+  const cx<T>* gin = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt;
   if constexpr (P2) {
-    // the last FFT stage writes the grid in natural order (with its halo)
+    // the first FFT stage reads the deconvolved, centred samples from memory
+    // (grid position j holds sample (j + nt/2) mod m, zero from nt on); the
+    // last writes the grid in natural order (with its halo)
+    const T* sn = static_cast<const T*>(I.sn);
+    auto src = [&](int b, int j) {
+      int n = j + nt / 2;
+      if (n >= m) n -= m;
+      return n < nt ? cscl(gin[(size_t)b * nt + n], sn[n]) : mk(T(0), T(0));
+    };
     const int step = m / I.fm.rad[I.fm.nst - 1];  // weight of the last digit in k
-    fft_lds_p2_sink<T, true>(gp, I.fm, twm, nl, m, 1, [&](int b, int blk, const auto& v) {
+    fft_lds_p2_src_sink<T, true>(gp, I.fm, twm, nl, m, 1, src, [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       cx<T>* g = gn + b * ls;
       const int k0 = dif_natural_p2(I.fm, blk * R);
@@ -1441,7 +1613,9 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
       }
     });
   } else {
-    fft_lds<T, P2, true>(gp, I.fm, twm, nl, m, 1);
+    load_deconv_pad<T, P2>(I, gin, nl, gp);
+    __syncthreads();
+    fft_lds<T, RS, true>(gp, I.fm, twm, nl, m, 1);
     const int32_t* permm = I.perm + I.fm.perm;
     for (int e = threadIdx.x; e < nl * m; e += kBlock) {
       int b, j;
@@ -1460,7 +1634,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
     interp_lines<T, 0, false, P2>(I, a, gn, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
   }
   __syncthreads();
-  fft_lds<T, P2, true>(fz, I.fz, twz, nl, nz, 1);
+  fft_lds<T, RS, true>(fz, I.fz, twz, nl, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
   for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
@@ -1473,8 +1647,9 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
 
 // Fused depth DFT + spreading + transposed a2 (operators R^T and A): one line
 // per work item; only the depth line is loaded and only the time line stored.
-template <typename T, bool P2, int TAPS>
+template <typename T, int RS, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz, nt = I.nt;
   const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;  // (global, as in k_line_nufft2)
@@ -1485,7 +1660,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
   copy_batched<2>(nz, [&](int e) { return in[e]; }, [&](int e, cx<T> v) { q[e] = v; });
   __syncthreads();
-  fft_lds<T, P2, true>(q, I.fz, twz, 1, nz, 1);
+  fft_lds<T, RS, true>(q, I.fz, twz, 1, nz, 1);
   const int32_t* permz = I.perm + I.fz.perm;
   auto fget = [&](int l) { return q[permz[l]]; };
   auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
@@ -1499,7 +1674,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
     spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put, put4);
   }
   __syncthreads();
-  ifft_pick_deconv<T, P2>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt, twm);
+  ifft_pick_deconv<T, RS>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt, twm);
   PAT_END_ITEM
 }
 
@@ -1599,8 +1774,9 @@ int items_of(const Inst& I, Items kind, bool nz) {
   return 0;
 }
 
-template <typename T, typename G, bool P2, int TAPS>
+template <typename T, typename G, int RS, int TAPS>
 struct Runner {
+  static constexpr bool P2 = RS == 0;
   int n;
   const Inst* h;
   const Inst* const* d;
@@ -1662,32 +1838,32 @@ struct Runner {
 
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
-    return launch(k_tr_x1_r2c<T, P2>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
+    return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
                   tm);
   }
   hipError_t x2(void* const* io, bool nz, int inv) {
     StageArgs a = base(IT_X2, nz, inv, io, io);
-    return launch(k_tr_x2<T, P2>, inv ? "idft_x2" : "dft_x2", a,
+    return launch(k_tr_x2<T, RS>, inv ? "idft_x2" : "dft_x2", a,
                   max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
   }
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_C2R, nz, 0, in, out);
-    return launch(k_tr_c2r_k1<T, P2>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
+    return launch(k_tr_c2r_k1<T, RS>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
                   st, tm);
   }
   hipError_t zfft(void* const* io, int inv) {
     StageArgs a = base(IT_LZ, true, inv, io, io);
-    return launch(k_line_fft<T, P2>, inv ? "idft_z" : "dft_z", a,
+    return launch(k_line_fft<T, RS>, inv ? "idft_z" : "dft_z", a,
                   max_over([](const Inst& I) { return lds_line_z(I, cs); }), st, tm);
   }
   hipError_t a2(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
-    return launch(k_line_a2<T, G, P2>, "deconv_pad_fft", a, max_over([](const Inst& I) { return lds_line_m(I, cs); }),
+    return launch(k_line_a2<T, G, RS>, "deconv_pad_fft", a, max_over([](const Inst& I) { return lds_line_m(I, cs); }),
                   st, tm);
   }
   hipError_t a2t(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
-    return launch(k_line_a2t<T, G, P2>, "ifft_pick_deconv", a,
+    return launch(k_line_a2t<T, G, RS>, "ifft_pick_deconv", a,
                   max_over([](const Inst& I) { return lds_line_m(I, cs); }), st, tm);
   }
   hipError_t interp(const void* const* in, void* const* out, int mode) {
@@ -1716,12 +1892,12 @@ struct Runner {
   }
   hipError_t nufft2(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LF, true, mode, in, out);
-    return launch(k_line_nufft2<T, P2, TAPS>, "nufft_fused", a,
+    return launch(k_line_nufft2<T, RS, TAPS>, "nufft_fused", a,
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LINE, true, mode, in, out);
-    return launch(k_line_nufft1<T, P2, TAPS>, "nufft_adjoint_fused", a,
+    return launch(k_line_nufft1<T, RS, TAPS>, "nufft_adjoint_fused", a,
                   max_over([](const Inst& I) { return lds_fused1(I, cs); }), st, tm);
   }
 };
@@ -1732,10 +1908,10 @@ struct Runner {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
-template <typename T, typename G, bool P2, int TAPS>
+template <typename T, typename G, int RS, int TAPS>
 hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
                     void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  Runner<T, G, P2, TAPS> r{n, h, d, hp, counters, 0, st, tm};
+  Runner<T, G, RS, TAPS> r{n, h, d, hp, counters, 0, st, tm};
   void* bg[kMaxBatch];
   void* bu[kMaxBatch];
   void* bf[kMaxBatch];
@@ -1792,6 +1968,16 @@ bool all_pow2(int n, const Inst* h) {
   return true;
 }
 
+// Largest radix over every FFT of the instances.
+int max_radix(int n, const Inst* h) {
+  int mx = 2;
+  for (int i = 0; i < n; ++i) {
+    for (const FftDesc* f : {&h[i].f1, &h[i].f2, &h[i].fm, &h[i].fz})
+      for (int s = 0; s < f->nst; ++s) mx = f->rad[s] > mx ? f->rad[s] : mx;
+  }
+  return mx;
+}
+
 bool all_taps(int n, const Inst* h, int taps) {
   for (int i = 0; i < n; ++i)
     if (h[i].taps != taps) return false;
@@ -1803,11 +1989,15 @@ hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const voi
                     void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
   const bool t12 = all_taps(n, h, 12);
   if (all_pow2(n, h)) {
-    if (t12) return run_op_t<T, G, true, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
-    return run_op_t<T, G, true, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+    if (t12) return run_op_t<T, G, 0, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+    return run_op_t<T, G, 0, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
   }
-  if (t12) return run_op_t<T, G, false, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
-  return run_op_t<T, G, false, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  if (max_radix(n, h) <= 8) {
+    if (t12) return run_op_t<T, G, 7, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+    return run_op_t<T, G, 7, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  }
+  if (t12) return run_op_t<T, G, 23, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  return run_op_t<T, G, 23, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
 }
 
 template <typename T, typename G>
@@ -1819,13 +2009,13 @@ hipError_t interp_only(const Inst& h, const Inst* dinst, const void* hpoly, cons
   void* o[1] = {out};
   if (h.taps == 12) {
     if (h.pow2) {
-      Runner<T, G, true, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+      Runner<T, G, 0, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
       return r.interp(in, o, 0);
     }
-    Runner<T, G, false, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+    Runner<T, G, 23, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
     return r.interp(in, o, 0);
   }
-  Runner<T, G, false, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
+  Runner<T, G, 23, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
   return r.interp(in, o, 0);
 }
 
@@ -1837,10 +2027,10 @@ hipError_t spread_only(const Inst& h, const Inst* dinst, const void* hpoly, cons
   const void* in[1] = {vals};
   void* o[1] = {grid};
   if (h.taps == 12) {
-    Runner<T, G, false, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+    Runner<T, G, 23, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
     return r.spread(in, o, 0);
   }
-  Runner<T, G, false, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
+  Runner<T, G, 23, 0> r{1, &h, d, hp, nullptr, 0, st, tm};
   return r.spread(in, o, 0);
 }
 
