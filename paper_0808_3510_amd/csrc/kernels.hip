@@ -1645,36 +1645,67 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   PAT_END_ITEM
 }
 
-// Fused depth DFT + spreading + transposed a2 (operators R^T and A): one line
-// per work item; only the depth line is loaded and only the time line stored.
+// Fused depth DFT + spreading + transposed a2 (operators R^T and A).  A work
+// item holds lpw_a lines: their depth DFTs run together (power-of-two
+// builds: the first stage reads the spectra from memory and the last writes
+// them in natural order), then each line is spread onto the grid and
+// transformed back, and only its time line is stored.
 template <typename T, int RS, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nz = I.nz, nt = I.nt;
+  const int lpw = I.lpw_a;
+  const int line0 = li * lpw;
+  const int nl = min(lpw, I.lines - line0);
   const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;  // (global, as in k_line_nufft2)
   const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
-  cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // m
-  cx<T>* q = grid + m;                                // nz
-  const SpreadLds<T> L = SpreadLds<T>::carve(q + nz, nz, I.taps);
-  const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)li * nz;
-  copy_batched<2>(nz, [&](int e) { return in[e]; }, [&](int e, cx<T> v) { q[e] = v; });
-  __syncthreads();
-  fft_lds<T, RS, true>(q, I.fz, twz, 1, nz, 1);
-  const int32_t* permz = I.perm + I.fz.perm;
-  auto fget = [&](int l) { return q[permz[l]]; };
+  const int sg = m > lpw * nz ? m : lpw * nz;
+  cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // depth-FFT scratch, then one grid line
+  cx<T>* qn = grid + sg;                              // lpw depth spectra, natural order
+  const SpreadLds<T> L = SpreadLds<T>::carve(qn + lpw * nz, nz, I.taps);
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nz;
+  if constexpr (P2) {
+    const int stepz = nz / I.fz.rad[I.fz.nst - 1];  // weight of the last digit in k
+    fft_lds_p2_src_sink<T, true>(
+        grid, I.fz, twz, nl, nz, 1, [&](int b, int pos) { return in[(size_t)b * nz + pos]; },
+        [&](int b, int blk, const auto& v) {
+          constexpr int R = sizeof(v) / sizeof(v[0]);
+          cx<T>* d = qn + b * nz;
+          const int k0 = dif_natural_p2(I.fz, blk * R);
+#pragma unroll
+          for (int r = 0; r < R; ++r) d[k0 + r * stepz] = v[r];
+        });
+  } else {
+    copy_batched<2>(nl * nz, [&](int e) { return in[e]; }, [&](int e, cx<T> v) { grid[e] = v; });
+    __syncthreads();
+    fft_lds<T, RS, true>(grid, I.fz, twz, nl, nz, 1);
+    const int32_t* permz = I.perm + I.fz.perm;
+    for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
+      int b, l;
+      divmod<P2>(e, nz, &b, &l);
+      qn[e] = grid[b * nz + permz[l]];
+    }
+    __syncthreads();
+  }
   auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
   auto put4 = [&](int j, const cx<T>* v) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) grid[j + c] = cconj(v[c]);
   };
-  if (TAPS > 0 && a.pair_ok) {
-    spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, li, a.mode, L, fget, put, put4);
-  } else {
-    spread_line<T, 0, false>(I, a, li, a.mode, L, fget, put, put4);
+  for (int b = 0; b < nl; ++b) {
+    // (spread_line's first barrier also ends every read of the previous
+    // line's grid)
+    const cx<T>* qb = qn + b * nz;
+    auto fget = [&](int l) { return qb[l]; };
+    if (TAPS > 0 && a.pair_ok) {
+      spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, line0 + b, a.mode, L, fget, put, put4);
+    } else {
+      spread_line<T, 0, false>(I, a, line0 + b, a.mode, L, fget, put, put4);
+    }
+    __syncthreads();
+    ifft_pick_deconv<T, RS>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)(line0 + b) * nt, twm);
   }
-  __syncthreads();
-  ifft_pick_deconv<T, RS>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)li * nt, twm);
   PAT_END_ITEM
 }
 
@@ -1755,7 +1786,7 @@ hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t sh
   return e;
 }
 
-enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LINE };
+enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LA, IT_LINE };
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -1769,6 +1800,7 @@ int items_of(const Inst& I, Items kind, bool nz) {
     case IT_LZ: return cdiv(I.lines, I.lpw_z);
     case IT_LI: return cdiv(I.lines, I.lpw_i);
     case IT_LF: return cdiv(I.lines, I.lpw_f);
+    case IT_LA: return cdiv(I.lines, I.lpw_a);
     case IT_LINE: return I.lines;
   }
   return 0;
@@ -1896,7 +1928,7 @@ struct Runner {
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
-    StageArgs a = base(IT_LINE, true, mode, in, out);
+    StageArgs a = base(IT_LA, true, mode, in, out);
     return launch(k_line_nufft1<T, RS, TAPS>, "nufft_adjoint_fused", a,
                   max_over([](const Inst& I) { return lds_fused1(I, cs); }), st, tm);
   }

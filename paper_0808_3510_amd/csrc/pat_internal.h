@@ -42,6 +42,7 @@ struct Inst {
   int32_t lpw_m, lpw_z, lpw_i;  // lines per work item: length-m FFT stages, depth FFT, interp/spread
   int32_t pow2;               // every FFT length is a power of two
   int32_t lpw_f;              // lines per work item of the fused line kernels
+  int32_t lpw_a;              // lines per work item of the fused adjoint kernel
   int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
   double c, K, alpha;
   double ck;                  // c*K
@@ -92,9 +93,11 @@ inline size_t lds_fused2(const Inst& I, size_t cs) {
   const size_t sp = (size_t)(I.m > I.nz ? I.m : I.nz);
   return (size_t)I.lpw_f * (sp + (size_t)I.m + I.taps) * cs;
 }
-// fused type-1 line kernel: one grid line, one depth line, the lists
+// fused type-1 line kernel: a region of max(m, lpw_a nz) (the depth FFTs,
+// then one grid line), lpw_a depth spectra in natural order, the lists
 inline size_t lds_fused1(const Inst& I, size_t cs) {
-  return ((size_t)I.m + I.nz) * cs + lds_spread(I, cs);
+  const size_t za = (size_t)I.lpw_a * I.nz;
+  return ((size_t)I.m > za ? (size_t)I.m : za) * cs + za * cs + lds_spread(I, cs);
 }
 
 }  // namespace pat

@@ -277,6 +277,10 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   while (I.lpw_i > 1 && lds_interp(I, cs) > 65536) --I.lpw_i;
   I.lpw_f = clampi(2048 / m, 1, 16);
   while (I.lpw_f > 1 && lds_fused2(I, cs) > 65536) --I.lpw_f;
+  // the adjoint kernel transforms lpw_a depth lines together (power-of-two
+  // builds), then spreads them one by one
+  I.lpw_a = I.pow2 ? clampi(m / g.nz, 1, 8) : 1;
+  while (I.lpw_a > 1 && lds_fused1(I, cs) > 48 * 1024) I.lpw_a /= 2;
   I.c = g.c;
   I.K = g.K;
   I.alpha = g.alpha;
