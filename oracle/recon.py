@@ -134,6 +134,25 @@ def reconstruct(p, g):
     return f[:, 0, :] if flat else f
 
 
+def reconstruct_with(p, g, kind: str, c: float, K: float = 3.0, alpha: float = 0.0):
+    """R with the nonuniform sums of eq. (fft-2) evaluated by one of the
+    methods Section 4 compares (``oracle.nufft.evaluate``: "kb", "sinc",
+    "linear", "nearest"; "direct" gives ``reconstruct``), for the
+    accuracy-against-time study."""
+    from .nufft import evaluate
+    _, flat = _as3(p, g)
+    G = transverse_dft(p, g)
+    l = int_freqs(g["nz"])
+    out = np.empty((g["n1"], g["n2"], g["nz"]), dtype=np.complex128)
+    for (a, b), (i1, i2) in _groups(g).items():
+        nu = nodes(a, b, l, g)
+        w = weights(a, b, l, g)
+        for x, y in zip(i1, i2):
+            out[x, y, :] = evaluate(G[x, y, :], nu, kind, c, K, alpha) * w
+    f = np.real(np.fft.ifftn(out, axes=(0, 1, 2)))
+    return f[:, 0, :] if flat else f
+
+
 def reconstruct_adjoint(q, g):
     """R^T (transpose for the real inner product): image-shaped ``q`` ->
     data-shaped output, ``Re( D_x^H T^H (W . D_xz q) ) / (n1 n2 nz)`` with
