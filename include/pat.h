@@ -59,6 +59,24 @@ typedef enum {
   PAT_F32_BF16GRID = 2  /* as PAT_F32, oversampled grid stored as bf16 */
 } pat_precision;
 
+/* How the nonuniform sums of eq. (fft-2) are evaluated (Section 4 compares
+ * these).  PAT_INTERP_KB is the NUFFT-based algorithm (Section 3) and the only
+ * one every entry point supports; the others serve the accuracy-against-time
+ * comparison and run pat_reconstruct and pat_nufft2_lines only (staged
+ * kernels), the remaining operators returning PAT_ERR_UNSUPPORTED:
+ *  SINC     the NUFFT algorithm with Psi = 1 on [-c pi, c pi] ("truncated
+ *           sinc"): no deconvolution, 2cK taps of sin(c pi u)/u.
+ *  LINEAR   interpolation-based: the zero-padded FFT at omega = j/c, linear
+ *           interpolation between floor(c omega) and the next grid point
+ *           (K and alpha are ignored; c >= 1).
+ *  NEAREST  as LINEAR with the nearest grid point, floor(c omega + 1/2). */
+typedef enum {
+  PAT_INTERP_KB = 0,
+  PAT_INTERP_SINC = 1,
+  PAT_INTERP_LINEAR = 2,
+  PAT_INTERP_NEAREST = 3
+} pat_interp;
+
 /*
  * Geometry and NUFFT parameters.
  *  ndim      2 (line detectors, nx[1] must be 1) or 3 (planar array).
@@ -75,6 +93,8 @@ typedef enum {
  *            0 selects 0.98*pi*(2c-1), just below the upper limit, as the
  *            numerical experiments of Section 5 do.
  *  precision a pat_precision.
+ *  interp    a pat_interp value; PAT_INTERP_KB, the Kaiser-Bessel NUFFT, is
+ *            the method of the paper.
  * Every FFT length (nx[0], nx[1], nz, c*nt) must factor into primes <= 23.
  * A line of c*nt (and of nz) complex values must fit one workgroup's LDS:
  * c*nt <= 8192 in float, 4096 in double; larger sizes make pat_plan_create
@@ -90,6 +110,7 @@ typedef struct {
   double dx, dt, dz, vs;
   double c, K, alpha;
   int32_t precision;
+  int32_t interp;
 } pat_geometry;
 
 typedef struct pat_plan pat_plan;

@@ -82,6 +82,8 @@ pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, 
   if (s != PAT_OK) return s;
   if (!aligned16(in) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
   if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  if (op != pat::OP_R && plan->inst.kind != PAT_INTERP_KB)
+    return set_err(PAT_ERR_UNSUPPORTED, "only the reconstruction runs with an interp other than PAT_INTERP_KB");
   if ((op == pat::OP_RT || op == pat::OP_A) && !plan->spread_ok)
     return set_err(PAT_ERR_UNSUPPORTED, "nz too large for the spreading lists of a depth line in LDS");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
@@ -216,6 +218,8 @@ pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void
   pat_status s = check_plan(plan);
   if (s != PAT_OK) return s;
   if (!aligned16(values) || !aligned16(grid)) return set_err(PAT_ERR_INVALID_ARG, "values/grid NULL or not 16-byte aligned");
+  if (plan->inst.kind != PAT_INTERP_KB)
+    return set_err(PAT_ERR_UNSUPPORTED, "spreading needs interp = PAT_INTERP_KB");
   if (!plan->spread_ok) return set_err(PAT_ERR_UNSUPPORTED, "nz too large for the spreading lists of a depth line in LDS");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
   hipError_t e = pat::run_spread(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, values, grid,

@@ -691,13 +691,32 @@ __device__ __forceinline__ void tap_weights_pairs(const StageArgs& a, T x, T* w)
   }
 }
 
-// Weight of tap t for a node (general path): the fitted polynomial from the
-// instance table, or the kernel itself when no fit met the tolerance.
+// Weight of tap t for a node (general path), offset delta = cK - 1/2 + x/2
+// from the node's first tap.  Kaiser-Bessel: the fitted polynomial from the
+// instance table, or the kernel itself when no fit met the tolerance.  The
+// other methods, scaled like the Kaiser-Bessel weights (which carry
+// Psi_hat / 2 against the 1 / (pi c) of the plan's scale):
+//   truncated sinc  Psi_hat(u) / 2 = sin(c pi u) / u, u = (delta - t) / c;
+//   linear          pi c (1 - |delta - t|);
+//   nearest         pi c.
 template <typename T>
 __device__ __forceinline__ T tap_weight(const Inst& I, int t, T x) {
   if (I.poly) return tap_poly<T>(static_cast<const T*>(I.poly_c) + t * (Deg<T>::v + 1), x);
   const T delta = T(I.ck - 0.5) + T(0.5) * x;
-  return kb_phi<T>((delta - T(t)) * T(1.0 / I.c), T(I.K), T(I.alpha));
+  const T d = delta - T(t);
+  switch (I.kind) {
+    case 1: {  // truncated sinc: c sin(pi d) / d
+      T s, co;
+      m_sincospi(d, &s, &co);
+      return d == T(0) ? T(kPi * I.c) : T(I.c) * s / d;
+    }
+    case 2: {
+      const T a = d < T(0) ? -d : d;
+      return a < T(1) ? T(kPi * I.c) * (T(1) - a) : T(0);
+    }
+    case 3: return T(kPi * I.c);
+    default: return kb_phi<T>(d * T(1.0 / I.c), T(I.K), T(I.alpha));
+  }
 }
 
 // Node position on the oversampled grid for nu (time-bin units): first tap
@@ -763,7 +782,8 @@ __device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, do
 template <typename T, int TAPS, bool PAIRS, bool P2>
 __device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m, double nup, const Inst& I,
                                             const StageArgs& a, cx<T>* vp, cx<T>* vn) {
-  const cx<T> ph = phase_mpi<T>(nup);
+  // (an uncentred grid, the interpolation-based methods, needs no node phase)
+  const cx<T> ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
   *vp = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, nup, I, a), ph);
   *vn = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, -nup, I, a), cconj(ph));
 }
@@ -1323,7 +1343,8 @@ __device__ __forceinline__ void load_deconv_pad(const Inst& I, const cx<T>* g, i
       [&](int e) {
         int b, j;
         divmod<P2>(e, m, &b, &j);
-        int n = j + nt / 2;
+        // centred: grid position j holds sample (j + nt/2) mod m; otherwise j
+        int n = I.centred ? j + nt / 2 : j;
         if (n >= m) n -= m;
         return n < nt ? cscl(g[(size_t)b * nt + n], sn[n]) : mk(T(0), T(0));
       },

@@ -14,6 +14,7 @@ constexpr int kMaxTaps = 64;     // 2cK
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one CDNA4 compute unit
+constexpr double kPi = 3.14159265358979323846264338327950288;
 // Degree of the per-tap polynomial that replaces the kernel evaluation
 // (float and double paths).
 constexpr int kPolyDegF = 8;
@@ -43,6 +44,8 @@ struct Inst {
   int32_t pow2;               // every FFT length is a power of two
   int32_t lpw_f;              // lines per work item of the fused line kernels
   int32_t lpw_a;              // lines per work item of the fused adjoint kernel
+  int32_t kind;               // pat_interp: how the nonuniform sums are evaluated
+  int32_t centred;            // grid from centred samples (KB, sinc) or not (linear, nearest)
   int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
   double c, K, alpha;
   double ck;                  // c*K

@@ -11,7 +11,6 @@ namespace pat {
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846264338327950288;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -194,10 +193,19 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
     msg << "unknown precision " << g.precision;
     return fail(PAT_ERR_INVALID_ARG);
   }
-  if (!std::isfinite(g.c) || g.c <= 1.0) {
-    msg << "oversampling c must be > 1 (got " << g.c << ")";
+  if (g.interp < PAT_INTERP_KB || g.interp > PAT_INTERP_NEAREST) {
+    msg << "unknown interp " << g.interp;
     return fail(PAT_ERR_INVALID_ARG);
   }
+  const bool kb = g.interp == PAT_INTERP_KB;
+  if (!std::isfinite(g.c) || (kb ? g.c <= 1.0 : g.c < 1.0)) {
+    msg << "oversampling c must be " << (kb ? "> 1" : ">= 1") << " (got " << g.c << ")";
+    return fail(PAT_ERR_INVALID_ARG);
+  }
+  // the interpolation-based methods: 2 taps (linear) or 1 (nearest), written
+  // as a window of 2cK grid points
+  if (g.interp == PAT_INTERP_LINEAR) g.K = 1.0 / g.c;
+  if (g.interp == PAT_INTERP_NEAREST) g.K = 0.5 / g.c;
   const double mreal = g.c * g.nt;
   if (!is_int(mreal) || ((long long)std::nearbyint(mreal)) % 2 != 0) {
     msg << "c*nt must be an even integer (got " << mreal << ")";
@@ -209,8 +217,9 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
     return fail(PAT_ERR_INVALID_ARG);
   }
   const double tr = 2.0 * g.c * g.K;
-  if (!is_int(tr) || std::nearbyint(tr) < 2 || std::nearbyint(tr) > kMaxTaps) {
-    msg << "2cK must be an integer in [2, " << kMaxTaps << "] (got " << tr << ")";
+  const int min_taps = kb ? 2 : 1;
+  if (!is_int(tr) || std::nearbyint(tr) < min_taps || std::nearbyint(tr) > kMaxTaps) {
+    msg << "2cK must be an integer in [" << min_taps << ", " << kMaxTaps << "] (got " << tr << ")";
     return fail(PAT_ERR_INVALID_ARG);
   }
   const int taps = (int)std::nearbyint(tr);
@@ -219,14 +228,18 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
     return fail(PAT_ERR_INVALID_ARG);
   }
   const double amax = kPi * (2.0 * g.c - 1.0);
-  if (g.alpha == 0.0) g.alpha = 0.98 * amax;
-  if (!std::isfinite(g.alpha) || !(g.alpha > kPi) || !(g.alpha < amax)) {
-    msg << "alpha must satisfy pi < alpha < pi(2c-1) = " << amax << " (got " << g.alpha << ")";
-    return fail(PAT_ERR_INVALID_ARG);
-  }
-  if (g.alpha * g.K > 700.0) {
-    msg << "alpha*K = " << g.alpha * g.K << " exceeds 700";
-    return fail(PAT_ERR_UNSUPPORTED);
+  if (kb) {
+    if (g.alpha == 0.0) g.alpha = 0.98 * amax;
+    if (!std::isfinite(g.alpha) || !(g.alpha > kPi) || !(g.alpha < amax)) {
+      msg << "alpha must satisfy pi < alpha < pi(2c-1) = " << amax << " (got " << g.alpha << ")";
+      return fail(PAT_ERR_INVALID_ARG);
+    }
+    if (g.alpha * g.K > 700.0) {
+      msg << "alpha*K = " << g.alpha * g.K << " exceeds 700";
+      return fail(PAT_ERR_UNSUPPORTED);
+    }
+  } else {
+    g.alpha = 0.0;  // no window parameter
   }
   const int prec = g.precision;
   const size_t cs = complex_bytes(prec);
@@ -314,12 +327,18 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   off = align256(off + (size_t)g.nt * rs);
   const int deg = prec == PAT_F64 ? kPolyDegD : kPolyDegF;
   std::vector<double> coef;
-  const double fit_err = fit_tap_polys(g.c, g.K, g.alpha, taps, deg, &coef);
-  I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 5e-8) ? 1 : 0;
+  I.kind = g.interp;
+  I.centred = (g.interp == PAT_INTERP_KB || g.interp == PAT_INTERP_SINC) ? 1 : 0;
+  if (kb) {
+    const double fit_err = fit_tap_polys(g.c, g.K, g.alpha, taps, deg, &coef);
+    I.poly = fit_err <= (prec == PAT_F64 ? 1e-13 : 5e-8) ? 1 : 0;
+  } else {
+    I.poly = 0;  // the other methods evaluate their weights directly
+  }
   {
     // the bf16 option stores the oversampled grid, so it runs the staged
     // kernels; the fused ones need their LDS within one workgroup's share
-    I.fused = (prec != PAT_F32_BF16GRID && lds_fused1(I, cs) <= kLdsMax && lds_fused2(I, cs) <= kLdsMax) ? 1 : 0;
+    I.fused = (kb && prec != PAT_F32_BF16GRID && lds_fused1(I, cs) <= kLdsMax && lds_fused2(I, cs) <= kLdsMax) ? 1 : 0;
   }
   const size_t off_poly = off;
   off = align256(off + coef.size() * rs);
@@ -364,10 +383,11 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.fz = desc_of(g.nz);
   // deconvolution factors e^{alpha K} / I0(K sqrt(alpha^2 - theta_n^2)),
   // theta_n = 2 pi n / nt - pi  (eq. nufft-c with Psi the Kaiser-Bessel window)
+  // (1 for the other methods: Psi = 1 there, or no window at all)
   for (int n = 0; n < g.nt; ++n) {
     const double th = 2.0 * kPi * ((double)n / (double)g.nt) - kPi;
     const double z = g.K * std::sqrt(g.alpha * g.alpha - th * th);
-    const double s = std::exp(g.alpha * g.K - z) / bessel_i0e(z);
+    const double s = kb ? std::exp(g.alpha * g.K - z) / bessel_i0e(z) : 1.0;
     const size_t o = off_sn + (size_t)n * rs;
     if (prec == PAT_F64) {
       put(p->blob, o, &s, 1);

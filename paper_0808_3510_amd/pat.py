@@ -35,7 +35,8 @@ class PatError(RuntimeError):
 class pat_geometry(ctypes.Structure):
     _fields_ = [("ndim", c_int32), ("nx", c_int32 * 2), ("nt", c_int32), ("nz", c_int32),
                 ("dx", c_double), ("dt", c_double), ("dz", c_double), ("vs", c_double),
-                ("c", c_double), ("K", c_double), ("alpha", c_double), ("precision", c_int32)]
+                ("c", c_double), ("K", c_double), ("alpha", c_double), ("precision", c_int32),
+                ("interp", c_int32)]
 
 
 _lib = None
@@ -178,7 +179,11 @@ def pat_last_error() -> str:
 
 # --------------------------------------------------------------------------
 
-def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, precision="f32") -> pat_geometry:
+INTERP = {"kb": 0, "sinc": 1, "linear": 2, "nearest": 3}
+
+
+def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, precision="f32",
+                  interp="kb") -> pat_geometry:
     g = pat_geometry()
     g.ndim = 2 if n2 == 1 else 3
     g.nx[0], g.nx[1] = int(n1), int(n2)
@@ -186,6 +191,7 @@ def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, p
     g.dx, g.dt, g.dz, g.vs = float(dx), float(dt), float(dz), float(vs)
     g.c, g.K, g.alpha = float(c), float(K), float(alpha)
     g.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    g.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
     return g
 
 
@@ -202,8 +208,8 @@ class Plan:
     """
 
     def __init__(self, n1, n2, nt, nz, dx=1.0, dt=1.0, dz=1.0, vs=1.0, c=2.0, K=3.0, alpha=0.0,
-                 precision="f32", device="cuda"):
-        self.geom = make_geometry(n1, n2, nt, nz, dx, dt, dz, vs, c, K, alpha, precision)
+                 precision="f32", device="cuda", interp="kb"):
+        self.geom = make_geometry(n1, n2, nt, nz, dx, dt, dz, vs, c, K, alpha, precision, interp)
         self.n1, self.n2, self.nt, self.nz = int(n1), int(n2), int(nt), int(nz)
         self.m = int(round(c * nt))
         self.lines = (self.n1 // 2 + 1) * self.n2

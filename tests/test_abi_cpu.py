@@ -44,6 +44,7 @@ def test_valid_plan_sizes():
     (dict(n1=58), 2),            # 29 is not a supported FFT radix
     (dict(n1=8192, n2=2), 2), (dict(nt=16384), 2), (dict(K=32.0, c=2.0), 1),
     (dict(nz=8192, precision="f64"), 2),   # a double depth line pair exceeds LDS
+    (dict(interp=7), 1), (dict(c=1.0, interp="kb"), 1), (dict(c=0.5, interp="linear"), 1),
 ])
 def test_invalid_geometry_is_rejected(kw, status):
     with pytest.raises(pat.PatError) as ei:
@@ -91,3 +92,12 @@ def test_batched_size_validation():
     finally:
         pat.pat_plan_destroy(p1)
         pat.pat_plan_destroy(p2)
+
+
+@pytest.mark.parametrize("kw", [dict(c=1.0, interp="linear"), dict(c=1.0, interp="nearest"),
+                                dict(c=2.0, interp="nearest"), dict(c=1.0, K=3.0, interp="sinc"),
+                                dict(c=4.0, interp="linear")])
+def test_interpolation_methods_make_plans(kw):
+    """The methods Section 4 compares get plans (2 taps, 1 tap, or 2cK)."""
+    ptr = pat.pat_plan_create(_geom(**kw))
+    pat.pat_plan_destroy(ptr)
