@@ -11,8 +11,9 @@ the roofline of the dominant kernel (per-kernel HIP events recorded by the
 library on the stream its kernels run on), the error against the closed-form
 phantom, the adjoint R^T, the stand-alone interpolation and spreading kernels,
 the batched launch over sixteen uneven instances and the 128^3 workload (as
-further line items), and the CPU oracle timed on a bounded sample of the same
-workload.
+further line items), the accuracy-against-time study of the interpolation
+methods Section 4 compares, and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -168,6 +169,37 @@ def batched_and_small(steps, torch, dev, pat, inputs, np):
     return out
 
 
+def interpolation_study(p_np, g, steps, torch, dev, pat, np):
+    """Accuracy against time for the ways of evaluating the nonuniform sums
+    that Section 4 compares (its Table 1 and Fig. 5), on this workload: each
+    method's R time and its relative l2 distance to the FP64 Kaiser-Bessel
+    reconstruction (c = 2, K = 3, which is within ~1e-11 of the direct sums)."""
+    n, nt, nz = g["n1"], g["nt"], g["nz"]
+
+    def plan_of(kind, c, prec):
+        return pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], c=c, precision=prec, device=dev,
+                        interp=kind)
+
+    ref_plan = plan_of("kb", 2.0, "f64")
+    ref = ref_plan.reconstruct(torch.from_numpy(p_np).to(dev, torch.float64))
+    del ref_plan
+    p32 = torch.from_numpy(p_np).to(dev, torch.float32)
+    rows = []
+    for kind, c, fused in [("kb", 2.0, True), ("kb", 2.0, False), ("sinc", 2.0, False)] + \
+            [(k, float(c), False) for k in ("linear", "nearest") for c in (1, 2, 4, 8, 16)]:
+        plan = plan_of(kind, c, "f32")
+        plan.set_fused(fused)
+        f = plan.reconstruct(p32)
+        for _ in range(2):
+            plan.reconstruct(p32, out=f)
+        ms = time_steps(plan, p32, f, steps, torch)
+        err = float((torch.linalg.vector_norm(f.double() - ref) / torch.linalg.vector_norm(ref)).item())
+        rows.append({"method": kind, "c": c, "kernels": "fused" if fused else "staged", "ms": ms,
+                     "relL2_vs_reference": err})
+        del plan, f
+    return {"reference": "FP64 Kaiser-Bessel NUFFT, c = 2, K = 3", "rows": rows}
+
+
 def cpu_baseline(p_np, g, f_gpu, budget_s, np):
     """The oracle (as it stands) on a bounded sample: its transverse DFT in
     full, plus its direct nonuniform DFT sums on a random sample of lines,
@@ -301,7 +333,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16grid"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and 128^3 workloads")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and 128^3 workloads and the interpolation-method study")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
@@ -418,6 +451,8 @@ def main():
     if not args.no_extra:
         print("[bench] batched and 128^3 workloads", file=sys.stderr, flush=True)
         out["other_workloads"] = batched_and_small(args.steps, torch, dev, pat, inputs, np)
+        print("[bench] interpolation methods", file=sys.stderr, flush=True)
+        out["interpolation_study"] = interpolation_study(p_np, g, max(3, args.steps // 4), torch, dev, pat, np)
     if not args.no_fp64 and args.precision != "f64":
         print("[bench] timing f64", file=sys.stderr, flush=True)
         plan64, f64, ms64, st64, _ = run_prec("f64")
