@@ -12,7 +12,8 @@ library on the stream its kernels run on), the error against the closed-form
 phantom, the adjoint R^T, the stand-alone interpolation and spreading kernels,
 the batched launch over sixteen uneven instances and the 128^3 workload (as
 further line items), the accuracy-against-time study of the interpolation
-methods Section 4 compares, and the CPU oracle timed on a bounded sample of
+methods Section 4 compares (on this workload and on Section 5's circle), and
+the CPU oracle timed on a bounded sample of
 the same workload.
 """
 from __future__ import annotations
@@ -200,6 +201,44 @@ def interpolation_study(p_np, g, steps, torch, dev, pat, np):
     return {"reference": "FP64 Kaiser-Bessel NUFFT, c = 2, K = 3", "rows": rows}
 
 
+def circle_experiment(steps, torch, dev, pat, inputs, np):
+    """Section 5's setting: the circular object, 512 line detectors on [0, 1),
+    data on (0, 1)^2 (nt = nz = 512).  Per evaluation method (Table 1 and the
+    c sweep of Fig. 5): R time and relative l2 distance to the direct Fourier
+    reconstruction f-dagger, stood in for by the FP64 Kaiser-Bessel R (c = 2,
+    K = 3: within 1e-11 of the direct sums).  Also the error with Gaussian
+    noise of variance 20 % of the data maximum, and against the phantom."""
+    p0, g, (x0, y0, a) = inputs.circle_case(512, 1006, 0.0)
+    pn, _, _ = inputs.circle_case(512, 1006, 0.2)
+    n = g["n1"]
+
+    def plan_of(kind, c, prec):
+        return pat.Plan(n, 1, g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, precision=prec,
+                        device=dev, interp=kind)
+
+    ref = plan_of("kb", 2.0, "f64").reconstruct(torch.from_numpy(p0).to(dev, torch.float64))
+    phantom = torch.from_numpy(inputs.circle_image(x0, y0, a, n, g["nz"], g["dx"], g["dz"])).to(dev)
+    p32 = torch.from_numpy(p0).to(dev, torch.float32)
+    rows = []
+    for kind, c in [("kb", 2.0), ("sinc", 2.0)] + [(k, float(c)) for k in ("linear", "nearest")
+                                                  for c in (1, 2, 4, 8, 16)]:
+        plan = plan_of(kind, c, "f32")
+        f = plan.reconstruct(p32)
+        for _ in range(2):
+            plan.reconstruct(p32, out=f)
+        ms = time_steps(plan, p32, f, steps, torch)
+        err = float((torch.linalg.vector_norm(f.double() - ref) / torch.linalg.vector_norm(ref)).item())
+        rows.append({"method": kind, "c": c, "ms": ms, "relL2_vs_direct": err})
+    kb = plan_of("kb", 2.0, "f32")
+    fn = kb.reconstruct(torch.from_numpy(pn).to(dev, torch.float32)).double()
+    f0 = kb.reconstruct(p32).double()
+    rel = lambda u, v: float((torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(v)).item())
+    return {"geometry": "2D, 512 line detectors, nt = nz = 512, dx = dt = dz = 1/512",
+            "circle": {"x0": x0, "y0": y0, "a": a}, "rows": rows,
+            "kb_noisy_relL2_vs_noiseless_direct": rel(fn, ref),
+            "kb_relL2_vs_phantom": rel(f0, phantom)}
+
+
 def cpu_baseline(p_np, g, f_gpu, budget_s, np):
     """The oracle (as it stands) on a bounded sample: its transverse DFT in
     full, plus its direct nonuniform DFT sums on a random sample of lines,
@@ -334,7 +373,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched and 128^3 workloads and the interpolation-method study")
+                    help="skip the batched and 128^3 workloads and the interpolation-method studies")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
@@ -453,6 +492,8 @@ def main():
         out["other_workloads"] = batched_and_small(args.steps, torch, dev, pat, inputs, np)
         print("[bench] interpolation methods", file=sys.stderr, flush=True)
         out["interpolation_study"] = interpolation_study(p_np, g, max(3, args.steps // 4), torch, dev, pat, np)
+        print("[bench] circle experiment", file=sys.stderr, flush=True)
+        out["circle_experiment"] = circle_experiment(args.steps, torch, dev, pat, inputs, np)
     if not args.no_fp64 and args.precision != "f64":
         print("[bench] timing f64", file=sys.stderr, flush=True)
         plan64, f64, ms64, st64, _ = run_prec("f64")

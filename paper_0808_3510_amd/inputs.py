@@ -158,3 +158,55 @@ def batched_case(seed: int = 5000, dtype=np.float64):
         p, geom, balls = planar_case(e, nb, seed + 1 + j, noise=0.0, dtype=dtype)
         cases.append((p, geom, balls))
     return cases
+
+
+# ---------------------------------------------------------------------------
+# 2D circular object of Section 5: f = (2/a) sqrt(a^2 - |x - x0|^2) inside the
+# circle, which is (1/a) times the projection of a uniform ball of radius a;
+# its data on y = 0 is therefore (1/a) times the line integral of the ball's
+# N-shaped pulse, in closed form
+#   p(x, t) = (1/a) Re[(s+ - s-) - t log((s+ + t + a) / (s- + t - a))],
+#   s+- = ((t +- a)^2 - rho^2)^(1/2),  rho = |(x, 0) - x0|,
+# principal branches (the sign under the root corrected; v_s = 1 units).
+
+def circle_image(x0: float, y0: float, a: float, nx: int, nz: int, dx: float, dz: float,
+                 dtype=np.float64) -> np.ndarray:
+    """``f[m, q]`` at ``(m dx, q dz)``."""
+    x = np.arange(nx)[:, None] * dx
+    y = np.arange(nz)[None, :] * dz
+    r2 = (x - x0) ** 2 + (y - y0) ** 2
+    return ((2.0 / a) * np.sqrt(np.maximum(a * a - r2, 0.0))).astype(dtype)
+
+
+def circle_traces(x0: float, y0: float, a: float, nx: int, nt: int, dx: float, dt: float,
+                  vs: float = 1.0, dtype=np.float64) -> np.ndarray:
+    """Closed-form data ``p[m, n]`` of the circle at detector ``m dx`` (plane
+    ``y = 0``) and time ``n dt`` (distances in units of ``vs`` time)."""
+    x = np.arange(nx)[:, None] * dx
+    t = vs * np.arange(nt)[None, :] * dt
+    rho2 = (x - x0) ** 2 + y0 * y0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        sp = np.sqrt(((t + a) ** 2 - rho2).astype(np.complex128))
+        sm = np.sqrt(((t - a) ** 2 - rho2).astype(np.complex128))
+        val = (sp - sm) - t * np.log((sp + t + a) / (sm + t - a))
+    p = np.real(val) / a
+    return np.where(np.isfinite(p), p, 0.0).astype(dtype)
+
+
+def circle_case(n: int = 512, seed: int = 1006, noise_var_frac: float = 0.0):
+    """The circle experiment: ``n`` line detectors on ``[0, 1)``, ``nt = nz = n``
+    (data on ``(0, 1)^2``, ``dx = dt = dz = 1/n``, ``v_s = 1``); centre and
+    radius drawn from the seed (the paper gives neither): ``a ~ U[0.1, 0.2]``,
+    ``x0 ~ U[0.3, 0.7]``, ``y0 ~ U[a + 0.1, 0.6]``.  ``noise_var_frac`` adds
+    Gaussian noise of variance that fraction of the largest data value."""
+    g = rng(seed)
+    a = float(g.uniform(0.1, 0.2))
+    x0 = float(g.uniform(0.3, 0.7))
+    y0 = float(g.uniform(a + 0.1, 0.6))
+    d = 1.0 / n
+    p = circle_traces(x0, y0, a, n, n, d, d)
+    if noise_var_frac > 0:
+        sigma = np.sqrt(noise_var_frac * np.abs(p).max())
+        p = p + sigma * g.standard_normal(p.shape)
+    geom = dict(n1=n, n2=1, nt=n, nz=n, dx=d, dt=d, dz=d, vs=1.0)
+    return p, geom, (x0, y0, a)
