@@ -170,6 +170,13 @@ def batched_and_small(steps, torch, dev, pat, inputs, np):
     return out
 
 
+# Kaiser-Bessel over the oversampling factors of Fig. 5.  c = 1 is outside
+# the window's range (deconvolving on [-pi, pi] needs alpha > pi, Section 3.2
+# bounds alpha below pi (2c - 1)); past c = 8 the 2cK taps are capped at 64,
+# so K shrinks.
+KB_SWEEP = [("kb", 2.0, 3.0), ("kb", 4.0, 3.0), ("kb", 8.0, 3.0), ("kb", 16.0, 2.0)]
+
+
 def interpolation_study(p_np, g, steps, torch, dev, pat, np):
     """Accuracy against time for the ways of evaluating the nonuniform sums
     that Section 4 compares (its Table 1 and Fig. 5), on this workload: each
@@ -177,8 +184,8 @@ def interpolation_study(p_np, g, steps, torch, dev, pat, np):
     reconstruction (c = 2, K = 3, which is within ~1e-11 of the direct sums)."""
     n, nt, nz = g["n1"], g["nt"], g["nz"]
 
-    def plan_of(kind, c, prec):
-        return pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], c=c, precision=prec, device=dev,
+    def plan_of(kind, c, prec, K=3.0):
+        return pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K, precision=prec, device=dev,
                         interp=kind)
 
     ref_plan = plan_of("kb", 2.0, "f64")
@@ -186,17 +193,21 @@ def interpolation_study(p_np, g, steps, torch, dev, pat, np):
     del ref_plan
     p32 = torch.from_numpy(p_np).to(dev, torch.float32)
     rows = []
-    for kind, c, fused in [("kb", 2.0, True), ("kb", 2.0, False), ("sinc", 2.0, False)] + \
-            [(k, float(c), False) for k in ("linear", "nearest") for c in (1, 2, 4, 8, 16)]:
-        plan = plan_of(kind, c, "f32")
+    for kind, c, K, fused in [(k, c, K, True) for k, c, K in KB_SWEEP] + [("kb", 2.0, 3.0, False),
+                                                                       ("sinc", 2.0, 3.0, False)] + \
+            [(k, float(c), 3.0, False) for k in ("linear", "nearest") for c in (1, 2, 4, 8, 16)]:
+        plan = plan_of(kind, c, "f32", K)
         plan.set_fused(fused)
         f = plan.reconstruct(p32)
         for _ in range(2):
             plan.reconstruct(p32, out=f)
         ms = time_steps(plan, p32, f, steps, torch)
         err = float((torch.linalg.vector_norm(f.double() - ref) / torch.linalg.vector_norm(ref)).item())
-        rows.append({"method": kind, "c": c, "kernels": "fused" if fused else "staged", "ms": ms,
-                     "relL2_vs_reference": err})
+        row = {"method": kind, "c": c, "kernels": "fused" if fused else "staged", "ms": ms,
+               "relL2_vs_reference": err}
+        if kind == "kb":
+            row["K"] = K
+        rows.append(row)
         del plan, f
     return {"reference": "FP64 Kaiser-Bessel NUFFT, c = 2, K = 3", "rows": rows}
 
@@ -212,23 +223,26 @@ def circle_experiment(steps, torch, dev, pat, inputs, np):
     pn, _, _ = inputs.circle_case(512, 1006, 0.2)
     n = g["n1"]
 
-    def plan_of(kind, c, prec):
-        return pat.Plan(n, 1, g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, precision=prec,
+    def plan_of(kind, c, prec, K=3.0):
+        return pat.Plan(n, 1, g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K, precision=prec,
                         device=dev, interp=kind)
 
     ref = plan_of("kb", 2.0, "f64").reconstruct(torch.from_numpy(p0).to(dev, torch.float64))
     phantom = torch.from_numpy(inputs.circle_image(x0, y0, a, n, g["nz"], g["dx"], g["dz"])).to(dev)
     p32 = torch.from_numpy(p0).to(dev, torch.float32)
     rows = []
-    for kind, c in [("kb", 2.0), ("sinc", 2.0)] + [(k, float(c)) for k in ("linear", "nearest")
-                                                  for c in (1, 2, 4, 8, 16)]:
-        plan = plan_of(kind, c, "f32")
+    for kind, c, K in KB_SWEEP + [("sinc", 2.0, 3.0)] + [(k, float(c), 3.0) for k in ("linear", "nearest")
+                                                         for c in (1, 2, 4, 8, 16)]:
+        plan = plan_of(kind, c, "f32", K)
         f = plan.reconstruct(p32)
         for _ in range(2):
             plan.reconstruct(p32, out=f)
         ms = time_steps(plan, p32, f, steps, torch)
         err = float((torch.linalg.vector_norm(f.double() - ref) / torch.linalg.vector_norm(ref)).item())
-        rows.append({"method": kind, "c": c, "ms": ms, "relL2_vs_direct": err})
+        row = {"method": kind, "c": c, "ms": ms, "relL2_vs_direct": err}
+        if kind == "kb":
+            row["K"] = K
+        rows.append(row)
     kb = plan_of("kb", 2.0, "f32")
     fn = kb.reconstruct(torch.from_numpy(pn).to(dev, torch.float32)).double()
     f0 = kb.reconstruct(p32).double()

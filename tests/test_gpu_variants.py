@@ -48,3 +48,31 @@ def test_methods_run_the_reconstruction_only():
     with pytest.raises(pat.PatError) as ei:
         plan.reconstruct_adjoint(q)
     assert ei.value.status == 2
+
+
+# Kaiser-Bessel over the oversampling factors of Fig. 5 (2cK taps capped at
+# 64, so K = 2 at c = 16).  The last geometry has an 8192-point grid line at
+# c = 16: its fused kernel holds 131 KB of LDS.
+KB_SWEEP = [(4.0, 3.0), (8.0, 3.0), (16.0, 2.0)]
+KB_GEOS = GEOS[:2] + [dict(n1=16, n2=1, nt=512, nz=64, dx=1 / 16, dt=1 / 512, dz=1 / 64, vs=1.0)]
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("c,K", KB_SWEEP)
+@pytest.mark.parametrize("gi", range(len(KB_GEOS)))
+def test_kaiser_bessel_oversampling_sweep(fused, prec, c, K, gi):
+    g = KB_GEOS[gi]
+    if prec == "f64" and c * g["nt"] * 16 > 65536:
+        pytest.skip("grid line beyond the FP64 line capacity (plan creation rejects it)")
+    print(f"R kb c={c} K={K} {prec} fused={fused} {g}", flush=True)
+    shape = (g["n1"], g["n2"], g["nt"]) if g["n2"] > 1 else (g["n1"], g["nt"])
+    p = inputs.random_array(shape, 500 + gi)
+    expect = recon.reconstruct_with(p, g, "kb", c, K)
+    plan = pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K,
+                    precision=prec, device="cuda")
+    plan.set_fused(fused)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    f = plan.reconstruct(torch.from_numpy(p).to("cuda", dt))
+    torch.cuda.synchronize()
+    assert relerr(f.cpu().double().numpy(), expect) < TOL[prec]
