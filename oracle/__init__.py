@@ -16,9 +16,11 @@ Modules
 ``nufft``  the paper's NUFFT (Section 3.1, Proposition on the NUFFT identity
            and the NUFFT algorithm), used only to pin the readings of its
            constant and phase against the direct sum.
+``cutoff`` the smooth cut-off w_cut of the partial-data model (eq. data-part,
+           Section 5) by nested quadrature of its defining convolution.
 
 Parity status: every function is pinned by a test under ``tests/`` against a
 closed form, a printed value of the paper, a library routine on a special case
 or a transpose identity; none is "parity unpinned".
 """
-from . import kb, nufft, recon  # noqa: F401
+from . import cutoff, kb, nufft, recon  # noqa: F401
