@@ -421,8 +421,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def run_prec(prec):
-        plan = pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], precision=prec, device=dev)
+    def run_prec(prec, cutoff=0.0):
+        plan = pat.Plan(n, n, nt, nz, g["dx"], g["dt"], g["dz"], g["vs"], precision=prec, device=dev,
+                        cutoff=cutoff)
         dt = torch.float64 if prec == "f64" else torch.float32
         p = torch.from_numpy(p_np).to(device=dev, dtype=dt)
         f = torch.empty((n, n, nz), dtype=dt, device=dev)
@@ -500,6 +501,12 @@ def main():
     plan.set_timing(False)
     out["adjoint_stage_ms"] = {k: sum(v) / len(v) for k, v in acc.items()}
     del plan, f, q, pt
+    # R with the smooth cut-off of the partial-data model (eps = 4 steps):
+    # the weights are applied inside the first transverse pass
+    planc, fc, msc, stc, _ = run_prec(args.precision, cutoff=4.0)
+    out["with_cutoff_eps4"] = {"ms_per_step": msc, "dft_x1_ms": stc.get("dft_x1"),
+                               "dft_x1_ms_without": stages.get("dft_x1")}
+    del planc, fc
     out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
     if not args.no_extra:
         print("[bench] batched and 128^3 workloads", file=sys.stderr, flush=True)

@@ -95,6 +95,17 @@ typedef enum {
  *  precision a pat_precision.
  *  interp    a pat_interp value; PAT_INTERP_KB, the Kaiser-Bessel NUFFT, is
  *            the method of the paper.
+ *  cutoff    radius eps, in sampling steps, of the smooth cut-off w_cut of
+ *            the partial-data model (eq. data-part; its construction at the
+ *            start of Section 5); 0 disables it (w = 1).  w_cut is the bump
+ *            exp(-1/(1 - |y|^2/eps^2)) of radius eps and unit mass, convolved
+ *            with the indicator of the data box shrunk by eps, in the
+ *            coordinates (x1, x2, t) (2D: (x1, t)) measured in sampling
+ *            steps, with data sample s of an axis of n samples at s and the
+ *            data box [0, n]: w is 0 on the box faces, 1 from 2 eps inwards,
+ *            smooth between.  The operators then act on w p: R(w p),
+ *            w R^T(q), w A(f), A^T(w p).  0 < eps <= 8 and 4 eps <= every
+ *            data axis length (n1, n2 in 3D, nt), else PAT_ERR_INVALID_ARG.
  * Every FFT length (nx[0], nx[1], nz, c*nt) must factor into primes <= 23.
  * A line of c*nt (and of nz) complex values must fit one workgroup's LDS:
  * c*nt <= 8192 in float, 4096 in double; larger sizes make pat_plan_create
@@ -111,6 +122,7 @@ typedef struct {
   double c, K, alpha;
   int32_t precision;
   int32_t interp;
+  double cutoff;
 } pat_geometry;
 
 typedef struct pat_plan pat_plan;

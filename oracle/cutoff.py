@@ -29,7 +29,7 @@ along chords of the ball (outer axis first; each inner interval is the chord
 of the ball at the outer coordinates, cut to the box), with
 ``numpy.polynomial.legendre.leggauss`` nodes.  The bump is flat to all orders
 at the sphere, so the nested rule converges fast; values are cached per
-distinct clipped box.
+distinct clipped box up to reflections and permutations of the axes.
 
 ``weights(g, eps)``  the (n1, n2, nt) array of w over the data grid;
 ``apply(x, g, eps)``  ``w * x`` for a data-shaped array (2D (n1, nt) accepted).
@@ -97,6 +97,14 @@ def weight_of(s, n, eps: float) -> float:
         lo = float(si) - (float(ni) - eps)   # s - y <= n - eps
         hi = float(si) - eps                 # s - y >= eps
         box.append((max(lo, -eps), min(hi, eps)))
+    # the bump is invariant under reflecting any axis and permuting the axes:
+    # boxes equal up to those motions share one value
+    canon = []
+    for lo, hi in box:
+        if hi >= eps > -lo:
+            lo, hi = -hi, -lo
+        canon.append((lo, hi))
+    box = sorted(canon)
     key = (eps, tuple(box))
     if key not in _cache:
         if any(hi <= lo for lo, hi in box):

@@ -1082,6 +1082,40 @@ __device__ __forceinline__ void st_pair(cx<T>* p, cx<T> a, cx<T> b) {
   }
 }
 
+// Smooth cut-off of the partial-data model (eq. data-part): data sample
+// (x1, x2, t) weighs W[b(x1)][b(x2)][b(t)], b(s) = min(s, n - s) clamped to
+// E = I.cut_e (the table and its index are described with Inst::cutw).
+__device__ __forceinline__ int cut_band(int s, int n, int E) {
+  const int d = min(s, n - s);
+  return d < E ? d : E;
+}
+
+// Copies the cut-off weights of column x2, W[b1][b(x2)][b3] for b1, b3 <= E,
+// into ws ((E+1)^2 values in LDS); visible to the block after its next barrier.
+template <typename T>
+__device__ __forceinline__ void cut_slice(const Inst& I, T* ws, int x2) {
+  const int E = I.cut_e, e1 = E + 1;
+  const int b2 = I.n2 > 1 ? cut_band(x2, I.n2, E) : E;
+  const T* W = static_cast<const T*>(I.cutw);
+  for (int e = threadIdx.x; e < e1 * e1; e += kBlock) {
+    const int b1 = e / e1, b3 = e - b1 * e1;
+    ws[e] = W[(b1 * e1 + b2) * e1 + b3];
+  }
+}
+
+// Multiplies v, the data samples t and t + 1 of row x1 (real and imaginary
+// part), by their cut-off weights from the column's slice ws (b2: the
+// column's band); samples at least E from every face keep weight 1.
+template <typename T>
+__device__ __forceinline__ void cut_pair(const Inst& I, const T* ws, int b2, int x1, int t, int len, cx<T>* v) {
+  const int E = I.cut_e;
+  const int b1 = cut_band(x1, I.n1, E);
+  if (b1 == E && b2 == E && t >= E && t + 1 <= len - E) return;
+  const T* w = ws + b1 * (E + 1);
+  v->x *= w[cut_band(t, len, E)];
+  v->y *= w[cut_band(t + 1, len, E)];
+}
+
 // ---------------------------------------------------------------------------
 // Transverse passes.  Tiles of consecutive samples (t or z, the contiguous
 // axis) by the full transform length; lanes run along the samples, so global
@@ -1108,6 +1142,14 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
   const int L = I.n1;
   const size_t rstride = (size_t)I.n2 * len;
   const T* in0 = in + (size_t)x2 * len + t0;
+  const bool cut = !a.len_nz && I.cut_e;  // data-side pass with a cut-off
+  // the column's cut-off weights, read from LDS while the tile is stored
+  T* cws = reinterpret_cast<T*>(buf + L * tb);
+  const int cb2 = cut && I.n2 > 1 ? cut_band(x2, I.n2, I.cut_e) : I.cut_e;
+  if (cut) {
+    cut_slice(I, cws, x2);
+    __syncthreads();
+  }
   if (len % 4 == 0 && tb % 2 == 0) {
     // column pairs: samples t0 + 4c .. t0 + 4c + 3 (len is a multiple of 4)
     const int hb = tb / 2;
@@ -1122,6 +1164,14 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
           return cx<cx<T>>{u[0], u[1]};
         },
         [&](int e, cx<cx<T>> v) {
+          if (cut) {
+            int x, c;
+            divmod<true>(e, hb, &x, &c);
+            if (t0 + 4 * c < len) {
+              cut_pair(I, cws, cb2, x, t0 + 4 * c, len, &v.x);
+              cut_pair(I, cws, cb2, x, t0 + 4 * c + 2, len, &v.y);
+            }
+          }
           buf[2 * e] = v.x;
           buf[2 * e + 1] = v.y;
         });
@@ -1134,7 +1184,14 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
           // samples t0 + 2b (real part) and t0 + 2b + 1 (imaginary part); len is even
           return t0 + 2 * b < len ? *reinterpret_cast<const cx<T>*>(in0 + x * rstride + 2 * b) : mk(T(0), T(0));
         },
-        [&](int e, cx<T> v) { buf[e] = v; });
+        [&](int e, cx<T> v) {
+          if (cut) {
+            int x, b;
+            divmod<true>(e, tb, &x, &b);
+            if (t0 + 2 * b < len) cut_pair(I, cws, cb2, x, t0 + 2 * b, len, &v);
+          }
+          buf[e] = v;
+        });
   }
   __syncthreads();
   fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
@@ -1248,6 +1305,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   const int half = L / 2;
   const size_t rstride = (size_t)I.n2 * len;
   const cx<T>* in0 = in + (size_t)x2 * len + t0;
+  const bool cut = !a.len_nz && I.cut_e;  // data-side pass with a cut-off
+  T* cws = reinterpret_cast<T*>(buf + L * tb);  // the column's cut-off weights
+  if (cut) cut_slice(I, cws, x2);
   copy_batched<4>(
       L * tb,
       [&](int e) {
@@ -1271,6 +1331,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
   fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
   const int32_t* perm = I.perm + I.f1.perm;
   T* out0 = out + (size_t)x2 * len + t0;
+  const int cb2 = cut && I.n2 > 1 ? cut_band(x2, I.n2, I.cut_e) : I.cut_e;
   if (len % 4 == 0 && tb % 2 == 0) {
     // four samples per lane (len is a multiple of 4)
     const int hb = tb / 2;
@@ -1279,8 +1340,12 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
       divmod<true>(e, hb, &x, &c);
       if (t0 + 4 * c < len) {
         const cx<T>* y = buf + perm[x] * tb + 2 * c;  // conj of x_a + i x_b
-        st_pair<T, true>(reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 4 * c), mk(y[0].x, -y[0].y),
-                         mk(y[1].x, -y[1].y));
+        cx<T> v0 = mk(y[0].x, -y[0].y), v1 = mk(y[1].x, -y[1].y);
+        if (cut) {
+          cut_pair(I, cws, cb2, x, t0 + 4 * c, len, &v0);
+          cut_pair(I, cws, cb2, x, t0 + 4 * c + 2, len, &v1);
+        }
+        st_pair<T, true>(reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 4 * c), v0, v1);
       }
     }
   } else {
@@ -1289,7 +1354,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
       divmod<true>(e, tb, &x, &b);
       if (t0 + 2 * b < len) {
         const cx<T> y = buf[perm[x] * tb + b];  // conj of x_a + i x_b
-        *reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 2 * b) = mk(y.x, -y.y);
+        cx<T> v = mk(y.x, -y.y);
+        if (cut) cut_pair(I, cws, cb2, x, t0 + 2 * b, len, &v);
+        *reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 2 * b) = v;
       }
     }
   }

@@ -11,6 +11,7 @@ namespace pat {
 constexpr int kMaxStages = 16;   // radix stages of one FFT
 constexpr int kMaxBatch = 32;    // instances in one batched call
 constexpr int kMaxTaps = 64;     // 2cK
+constexpr double kMaxCutoff = 8.0;  // cut-off radius in sampling steps
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one CDNA4 compute unit
@@ -47,6 +48,7 @@ struct Inst {
   int32_t kind;               // pat_interp: how the nonuniform sums are evaluated
   int32_t centred;            // grid from centred samples (KB, sinc) or not (linear, nearest)
   int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
+  int32_t cut_e;              // cut-off band width E = ceil(2 eps) in samples; 0: no cut-off
   double c, K, alpha;
   double ck;                  // c*K
   // node and weight:  nu+^2 = a1 k1^2 + a2 k2^2 + b l^2 ;  W = wcoef |l| / nu+
@@ -61,6 +63,10 @@ struct Inst {
   const int32_t* perm;   // int32[]
   const void* sn;        // T[nt]: e^{alpha K} / I0(K sqrt(alpha^2 - theta_n^2))
   const void* poly_c;    // T[taps][deg+1]: tap t as a polynomial in x = 2 (delta - cK) + 1
+  // T[(E+1)^3]: cut-off weight by the samples' distances d_i = min(s, n - s)
+  // to the data box faces per axis (x1, x2, t), each clamped to E; entry
+  // ((d1 (E+1) + d2) (E+1) + d3).  2D plans use d2 = E.
+  const void* cutw;
   // workspace byte offsets
   int64_t off_g, off_u, off_f;
 };
@@ -70,7 +76,11 @@ struct Inst {
 // here; the host plan uses the same functions for its capacity checks and the
 // launchers for the dynamic LDS request.
 // (FFT kernels start with the twiddle table of each length they transform)
-inline size_t lds_tile_x1(const Inst& I, size_t cs) { return (size_t)I.n1 * (I.tb + 1) * cs; }
+// (x1 passes: plus one column's (E+1)^2 cut-off weights when a cut-off is set)
+inline size_t lds_tile_x1(const Inst& I, size_t cs) {
+  const size_t e1 = (size_t)I.cut_e + 1;
+  return (size_t)I.n1 * (I.tb + 1) * cs + (I.cut_e ? e1 * e1 * (cs / 2) : 0);
+}
 inline size_t lds_tile_x2(const Inst& I, size_t cs) { return (size_t)I.n2 * (I.tb + 1) * cs; }
 inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.nz * (I.lpw_z + 1) * cs; }
 inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.m * (I.lpw_m + 1) * cs; }

@@ -120,6 +120,121 @@ double fit_tap_polys(double c, double K, double a, int taps, int D, std::vector<
   return fmax > 0 ? emax / fmax : 0.0;
 }
 
+// Gauss-Legendre nodes and weights of order q on [-1, 1]: Newton's method on
+// the three-term recurrence of the Legendre polynomials.
+void gauss_legendre(int q, std::vector<double>* x, std::vector<double>* w) {
+  x->assign(q, 0.0);
+  w->assign(q, 0.0);
+  for (int i = 0; i < (q + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (q + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = -z;
+    (*x)[q - 1 - i] = z;
+    (*w)[i] = (*w)[q - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Cut-off weights of the partial-data model (eq. data-part; w_cut as built at
+// the start of Section 5, with the unit-mass bump exp(-1/(1 - |y|^2/eps^2))
+// of radius eps convolved with the indicator of the data box shrunk by eps).
+// A sample at distance d_i (in steps) from the nearer face of axis i sees the
+// part of the bump with y_i <= d_i - eps on that axis (a reflection for an
+// upper face; the bump is radial); d_i >= E = ceil(2 eps) leaves the axis
+// unconstrained, and 4 eps <= n_i keeps the other face out of reach.  The
+// constraint values -eps + j cut [-eps, eps] into E cells per axis; each cell
+// of the dim-dimensional grid is integrated by Gauss-Legendre (order q per
+// cell piece, about 256 nodes per axis), and prefix sums over the cells give
+// W[d1][d2][d3] (index ((d1 (E+1) + d2) (E+1) + d3)), normalised by the
+// total.  In 2D the table is over (d1, d3) and repeated along d2.
+void cutoff_table(double eps, int dim, std::vector<double>* W) {
+  const int E = (int)std::ceil(2.0 * eps - 1e-12);
+  const int q = std::max(16, 256 / E);
+  std::vector<double> gx, gw;
+  gauss_legendre(q, &gx, &gw);
+  // nodes and weights of every cell, cell j = [-eps + j, min(-eps + j + 1, eps)]
+  std::vector<double> y((size_t)E * q), wy((size_t)E * q);
+  for (int j = 0; j < E; ++j) {
+    const double a = -eps + j, b = std::min(-eps + j + 1.0, eps), h = 0.5 * (b - a);
+    for (int k = 0; k < q; ++k) {
+      y[(size_t)j * q + k] = a + h * (gx[k] + 1.0);
+      wy[(size_t)j * q + k] = h * gw[k];
+    }
+  }
+  const double ie2 = 1.0 / (eps * eps);
+  auto bump = [&](double r2) {
+    const double u = 1.0 - r2 * ie2;
+    return u > 0.0 ? std::exp(-1.0 / u) : 0.0;
+  };
+  const int e1 = E + 1;
+  W->assign((size_t)e1 * e1 * e1, 0.0);
+  if (dim == 3) {
+    // cell integrals (symmetric under permutations of the axes)
+    std::vector<double> C((size_t)E * E * E, 0.0);
+    for (int a = 0; a < E; ++a)
+      for (int b = a; b < E; ++b)
+        for (int c = b; c < E; ++c) {
+          double s = 0.0;
+          for (int i = 0; i < q; ++i) {
+            const double y1 = y[(size_t)a * q + i], w1 = wy[(size_t)a * q + i];
+            for (int j = 0; j < q; ++j) {
+              const double y2 = y[(size_t)b * q + j], w12 = w1 * wy[(size_t)b * q + j];
+              const double r12 = y1 * y1 + y2 * y2;
+              if (r12 >= eps * eps) continue;
+              for (int k = 0; k < q; ++k) {
+                const double y3 = y[(size_t)c * q + k];
+                s += w12 * wy[(size_t)c * q + k] * bump(r12 + y3 * y3);
+              }
+            }
+          }
+          const int p[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
+          for (auto& t : p) C[((size_t)t[0] * E + t[1]) * E + t[2]] = s;
+        }
+    for (int d1 = 1; d1 <= E; ++d1)
+      for (int d2 = 1; d2 <= E; ++d2)
+        for (int d3 = 1; d3 <= E; ++d3) {
+          auto at = [&](int i, int j, int k) -> double& { return (*W)[((size_t)i * e1 + j) * e1 + k]; };
+          at(d1, d2, d3) = C[((size_t)(d1 - 1) * E + (d2 - 1)) * E + (d3 - 1)] + at(d1 - 1, d2, d3) +
+                           at(d1, d2 - 1, d3) + at(d1, d2, d3 - 1) - at(d1 - 1, d2 - 1, d3) -
+                           at(d1 - 1, d2, d3 - 1) - at(d1, d2 - 1, d3 - 1) + at(d1 - 1, d2 - 1, d3 - 1);
+        }
+    const double tot = (*W)[((size_t)E * e1 + E) * e1 + E];
+    for (double& v : *W) v /= tot;
+  } else {
+    std::vector<double> C((size_t)E * E, 0.0);
+    for (int a = 0; a < E; ++a)
+      for (int b = a; b < E; ++b) {
+        double s = 0.0;
+        for (int i = 0; i < q; ++i)
+          for (int j = 0; j < q; ++j) {
+            const double y1 = y[(size_t)a * q + i], y2 = y[(size_t)b * q + j];
+            s += wy[(size_t)a * q + i] * wy[(size_t)b * q + j] * bump(y1 * y1 + y2 * y2);
+          }
+        C[(size_t)a * E + b] = C[(size_t)b * E + a] = s;
+      }
+    std::vector<double> S((size_t)e1 * e1, 0.0);
+    for (int d1 = 1; d1 <= E; ++d1)
+      for (int d3 = 1; d3 <= E; ++d3)
+        S[(size_t)d1 * e1 + d3] = C[(size_t)(d1 - 1) * E + (d3 - 1)] + S[(size_t)(d1 - 1) * e1 + d3] +
+                                  S[(size_t)d1 * e1 + d3 - 1] - S[(size_t)(d1 - 1) * e1 + d3 - 1];
+    const double tot = S[(size_t)E * e1 + E];
+    for (int d1 = 0; d1 <= E; ++d1)
+      for (int d2 = 0; d2 <= E; ++d2)
+        for (int d3 = 0; d3 <= E; ++d3) (*W)[((size_t)d1 * e1 + d2) * e1 + d3] = S[(size_t)d1 * e1 + d3] / tot;
+  }
+}
+
 bool is_pow2(int L) { return L > 0 && (L & (L - 1)) == 0; }
 
 int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -196,6 +311,18 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   if (g.interp < PAT_INTERP_KB || g.interp > PAT_INTERP_NEAREST) {
     msg << "unknown interp " << g.interp;
     return fail(PAT_ERR_INVALID_ARG);
+  }
+  {
+    const double e = g.cutoff;
+    const int n2c = g.ndim == 3 ? g.nx[1] : g.nt;
+    if (!std::isfinite(e) || e < 0.0 || e > kMaxCutoff) {
+      msg << "cutoff must be 0 or in (0, " << kMaxCutoff << "] sampling steps (got " << e << ")";
+      return fail(PAT_ERR_INVALID_ARG);
+    }
+    if (e > 0.0 && (4.0 * e > g.nx[0] || 4.0 * e > n2c || 4.0 * e > g.nt)) {
+      msg << "cutoff " << e << " needs 4 eps <= every data axis length";
+      return fail(PAT_ERR_INVALID_ARG);
+    }
   }
   const bool kb = g.interp == PAT_INTERP_KB;
   if (!std::isfinite(g.c) || (kb ? g.c <= 1.0 : g.c < 1.0)) {
@@ -277,6 +404,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   I.h1 = n1 / 2 + 1;
   I.lines = I.h1 * n2;
   I.taps = taps;
+  I.cut_e = g.cutoff > 0.0 ? (int)std::ceil(2.0 * g.cutoff - 1e-12) : 0;  // cut-off band, steps
   I.tb = prec == PAT_F64 ? 8 : 16;
   while (I.tb > 1 && std::max(lds_tile_x1(I, cs), lds_tile_x2(I, cs)) > 65536) I.tb /= 2;
   I.pow2 = is_pow2(n1) && is_pow2(n2) && is_pow2(m) && is_pow2(g.nz);
@@ -342,6 +470,10 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   }
   const size_t off_poly = off;
   off = align256(off + coef.size() * rs);
+  std::vector<double> cutw;
+  if (I.cut_e) cutoff_table(g.cutoff, g.ndim, &cutw);
+  const size_t off_cut = off;
+  off = align256(off + cutw.size() * rs);
   const size_t total = off;
 
   p->blob.assign(total, 0);
@@ -396,6 +528,15 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
       put(p->blob, o, &f, 1);
     }
   }
+  for (size_t i = 0; i < cutw.size(); ++i) {
+    const size_t o = off_cut + i * rs;
+    if (prec == PAT_F64) {
+      put(p->blob, o, &cutw[i], 1);
+    } else {
+      const float f = (float)cutw[i];
+      put(p->blob, o, &f, 1);
+    }
+  }
   for (size_t i = 0; i < coef.size(); ++i) {
     const size_t o = off_poly + i * rs;
     if (prec == PAT_F64) {
@@ -422,6 +563,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   p->off_perm = off_perm;
   p->off_sn = off_sn;
   p->off_poly = off_poly;
+  p->off_cut = off_cut;
   p->table_bytes = total;
   return PAT_OK;
 }
@@ -432,6 +574,7 @@ void bind_table(pat_plan* p, void* table_dev) {
   p->inst.perm = reinterpret_cast<const int32_t*>(base + p->off_perm);
   p->inst.sn = base + p->off_sn;
   p->inst.poly_c = base + p->off_poly;
+  p->inst.cutw = p->inst.cut_e ? base + p->off_cut : nullptr;
   std::memcpy(p->blob.data() + p->off_desc, &p->inst, sizeof(Inst));
   p->table_dev = table_dev;
 }

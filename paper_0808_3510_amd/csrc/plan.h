@@ -13,7 +13,7 @@ struct pat_plan {
   int prec = 0;            // pat_precision
   pat::Inst inst;          // host copy of the device descriptor
   std::vector<unsigned char> blob;  // host image of the device table buffer
-  size_t off_desc = 0, off_tw = 0, off_perm = 0, off_sn = 0, off_poly = 0;
+  size_t off_desc = 0, off_tw = 0, off_perm = 0, off_sn = 0, off_poly = 0, off_cut = 0;
   size_t table_bytes = 0, ws_bytes = 0;
   void* table_dev = nullptr;
   bool uploaded = false;

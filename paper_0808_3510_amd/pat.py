@@ -36,7 +36,7 @@ class pat_geometry(ctypes.Structure):
     _fields_ = [("ndim", c_int32), ("nx", c_int32 * 2), ("nt", c_int32), ("nz", c_int32),
                 ("dx", c_double), ("dt", c_double), ("dz", c_double), ("vs", c_double),
                 ("c", c_double), ("K", c_double), ("alpha", c_double), ("precision", c_int32),
-                ("interp", c_int32)]
+                ("interp", c_int32), ("cutoff", c_double)]
 
 
 _lib = None
@@ -183,7 +183,7 @@ INTERP = {"kb": 0, "sinc": 1, "linear": 2, "nearest": 3}
 
 
 def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, precision="f32",
-                  interp="kb") -> pat_geometry:
+                  interp="kb", cutoff=0.0) -> pat_geometry:
     g = pat_geometry()
     g.ndim = 2 if n2 == 1 else 3
     g.nx[0], g.nx[1] = int(n1), int(n2)
@@ -192,6 +192,7 @@ def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, p
     g.c, g.K, g.alpha = float(c), float(K), float(alpha)
     g.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     g.interp = INTERP[interp] if isinstance(interp, str) else int(interp)
+    g.cutoff = float(cutoff)
     return g
 
 
@@ -202,14 +203,16 @@ def _stream(device) -> int:
 class Plan:
     """A plan, its uploaded table and its workspace on one device.
 
-    ``n2 = 1`` selects the 2D line geometry.  Arrays are ``(n1, n2, nt)`` /
+    ``n2 = 1`` selects the 2D line geometry; ``cutoff`` > 0 applies the smooth
+    cut-off of that radius (in sampling steps) on the data side (see
+    ``pat_geometry.cutoff``).  Arrays are ``(n1, n2, nt)`` /
     ``(n1, n2, nz)`` (or ``(n1, nt)`` / ``(n1, nz)`` in 2D), contiguous, float64
     for ``precision="f64"`` and float32 otherwise.
     """
 
     def __init__(self, n1, n2, nt, nz, dx=1.0, dt=1.0, dz=1.0, vs=1.0, c=2.0, K=3.0, alpha=0.0,
-                 precision="f32", device="cuda", interp="kb"):
-        self.geom = make_geometry(n1, n2, nt, nz, dx, dt, dz, vs, c, K, alpha, precision, interp)
+                 precision="f32", device="cuda", interp="kb", cutoff=0.0):
+        self.geom = make_geometry(n1, n2, nt, nz, dx, dt, dz, vs, c, K, alpha, precision, interp, cutoff)
         self.n1, self.n2, self.nt, self.nz = int(n1), int(n2), int(nt), int(nz)
         self.m = int(round(c * nt))
         self.lines = (self.n1 // 2 + 1) * self.n2

@@ -2,6 +2,8 @@
 symbol, and the host-only plan creation validates its geometry."""
 import ctypes
 
+import numpy as np
+
 import pytest
 
 from paper_0808_3510_amd import pat
@@ -45,6 +47,9 @@ def test_valid_plan_sizes():
     (dict(n1=8192, n2=2), 2), (dict(nt=16384), 2), (dict(K=32.0, c=2.0), 1),
     (dict(nz=8192, precision="f64"), 2),   # a double depth line pair exceeds LDS
     (dict(interp=7), 1), (dict(c=1.0, interp="kb"), 1), (dict(c=0.5, interp="linear"), 1),
+    (dict(cutoff=-1.0), 1), (dict(cutoff=8.5, n1=64, n2=64, nt=64), 1), (dict(cutoff=float("nan")), 1),
+    (dict(cutoff=4.5), 1),       # 4 eps exceeds the 16 detectors
+    (dict(cutoff=3.0, n2=1, nt=8), 1),     # ... or the 8 time samples (2D)
 ])
 def test_invalid_geometry_is_rejected(kw, status):
     with pytest.raises(pat.PatError) as ei:
@@ -101,3 +106,19 @@ def test_interpolation_methods_make_plans(kw):
     """The methods Section 4 compares get plans (2 taps, 1 tap, or 2cK)."""
     ptr = pat.pat_plan_create(_geom(**kw))
     pat.pat_plan_destroy(ptr)
+
+
+@pytest.mark.parametrize("eps,n2", [(0.5, 16), (2.0, 16), (2.5, 1), (4.0, 16)])
+def test_cutoff_plans_carry_a_weight_table(eps, n2):
+    """A cut-off adds its (E+1)^3 weight table, E = ceil(2 eps), to the plan's
+    device tables."""
+    base = pat.pat_plan_create(_geom(n2=n2))
+    cut = pat.pat_plan_create(_geom(n2=n2, cutoff=eps))
+    try:
+        e = int(np.ceil(2 * eps))
+        extra = pat.pat_plan_sizes(cut)[0] - pat.pat_plan_sizes(base)[0]
+        assert (e + 1) ** 3 * 4 <= extra <= (e + 1) ** 3 * 4 + 256
+        assert pat.pat_plan_sizes(cut)[1] == pat.pat_plan_sizes(base)[1]
+    finally:
+        pat.pat_plan_destroy(base)
+        pat.pat_plan_destroy(cut)
