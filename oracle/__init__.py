@@ -14,8 +14,10 @@ Modules
            direct nonuniform DFT sums.
 ``kb``     the Kaiser-Bessel window and its Fourier transform (Section 3.2).
 ``nufft``  the paper's NUFFT (Section 3.1, Proposition on the NUFFT identity
-           and the NUFFT algorithm), used only to pin the readings of its
-           constant and phase against the direct sum.
+           and the NUFFT algorithm), which pins the readings of its constant
+           and phase against the direct sum, and the other evaluations of the
+           nonuniform sums that Section 4 compares (truncated sinc, linear
+           and nearest interpolation of the oversampled FFT).
 ``cutoff`` the smooth cut-off w_cut of the partial-data model (eq. data-part,
            Section 5) by nested quadrature of its defining convolution.
 
