@@ -558,6 +558,7 @@ struct StageArgs {
   const void* in[kMaxBatch];
   void* out[kMaxBatch];
   uint32_t* counter;  // persistent queue, or nullptr: items blockIdx.x + i gridDim.x
+  int32_t item_slot;  // with a counter: byte offset of the item slot in dynamic LDS
   int32_t len_nz;     // transverse passes: lines have nz (else nt) samples
   int32_t mode;       // FFT direction (0 forward, 1 inverse) / interp, spread mode
   int32_t pair_ok;    // pc holds every instance's mirrored tap-pair polynomials
@@ -749,7 +750,7 @@ __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, do
 // sum_t phi((delta - t)/c) U[(j0 + t) mod m] at nu.  With PAIRS the grid line
 // carries a halo (U[m + t] = U[t], t < TAPS - 1), so the taps read
 // U[j0 .. j0 + TAPS - 1] without wrapping.
-template <typename T, int TAPS, bool PAIRS, bool P2>
+template <typename T, int TAPS, bool PAIRS, bool P2, bool HALO = true>
 __device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, double nu, const Inst& I,
                                          const StageArgs& a) {
   const Node<T> nd = make_node<T, P2>(nu, I, m, inv_m);
@@ -757,12 +758,24 @@ __device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, do
   if constexpr (PAIRS) {
     T w[TAPS];
     tap_weights_pairs<T, TAPS>(a, nd.x, w);
-    const cx<T>* u = U + nd.j0;
+    if (HALO || nd.j0 <= m - TAPS) {
+      const cx<T>* u = U + nd.j0;
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
-      const cx<T> g = u[t];
-      acc.x += w[t] * g.x;
-      acc.y += w[t] * g.y;
+      for (int t = 0; t < TAPS; ++t) {
+        const cx<T> g = u[t];
+        acc.x += w[t] * g.x;
+        acc.y += w[t] * g.y;
+      }
+    } else {
+      // the window runs past the end of a line without halo: wrap its taps
+#pragma unroll
+      for (int t = 0; t < TAPS; ++t) {
+        int j = nd.j0 + t;
+        j -= j >= m ? m : 0;
+        const cx<T> g = U[j];
+        acc.x += w[t] * g.x;
+        acc.y += w[t] * g.y;
+      }
     }
   } else {
     int jm = nd.j0;
@@ -779,13 +792,13 @@ __device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, do
 
 // The type-2 values at the node pair +nup and -nup:
 // exp(-+i pi nup) sum_t phi(...) U[...]; the two phases are conjugate.
-template <typename T, int TAPS, bool PAIRS, bool P2>
+template <typename T, int TAPS, bool PAIRS, bool P2, bool HALO = true>
 __device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m, double nup, const Inst& I,
                                             const StageArgs& a, cx<T>* vp, cx<T>* vn) {
   // (an uncentred grid, the interpolation-based methods, needs no node phase)
   const cx<T> ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
-  *vp = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, nup, I, a), ph);
-  *vn = cmul(tap_sum<T, TAPS, PAIRS, P2>(U, m, inv_m, -nup, I, a), cconj(ph));
+  *vp = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, nup, I, a), ph);
+  *vn = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, -nup, I, a), cconj(ph));
 }
 
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
@@ -804,9 +817,9 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
 // (A^T): pairs |l| = 0 .. nz/2; outputs l and -l both get the mean of the two
 // values, no weight.  put(e, value) receives output e = b*nz + l_index.
 // akl[b] holds line b's |K_x|^2 term.
-template <typename T, int TAPS, bool PAIRS, bool P2, typename Put>
+template <typename T, int TAPS, bool PAIRS, bool P2, bool HALO = true, typename Ak, typename Put>
 __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, const cx<T>* U, int ls,
-                                             const double* akl, int nl, int mode, Put put) {
+                                             Ak akl, int nl, int mode, Put put) {
   const int m = I.m, nz = I.nz, half = nz / 2;
   const double wsc = I.wcoef * I.scale;
   const double inv_m = 1.0 / (double)m;
@@ -820,9 +833,9 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
       p = e - b * per;
     }
     const int la = mode == 0 ? p + 1 : p;
-    const double nup = sqrt_nt(akl[b] + I.b * (double)la * (double)la);
+    const double nup = sqrt_nt(akl(b) + I.b * (double)la * (double)la);
     cx<T> vp, vn;
-    interp_pair<T, TAPS, PAIRS, P2>(U + b * ls, m, inv_m, nup, I, a, &vp, &vn);
+    interp_pair<T, TAPS, PAIRS, P2, HALO>(U + b * ls, m, inv_m, nup, I, a, &vp, &vn);
     const int o = b * nz;
     if (mode == 0) {
       const double w = wsc * (double)la * rcp_nt(nup);
@@ -1006,9 +1019,15 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
   }
 }
 
-__device__ __forceinline__ int next_item(const StageArgs& a, int iter, int* s_item) {
+extern __shared__ __align__(16) unsigned char pat_smem[];
+
+// With a work counter, thread 0 takes the next item and hands it to the
+// block through a slot at byte a.item_slot of the dynamic LDS, past every
+// buffer of the kernel (the launcher adds it to the request).
+__device__ __forceinline__ int next_item(const StageArgs& a, int iter) {
   int item;
   if (a.counter) {
+    int* s_item = reinterpret_cast<int*>(pat_smem + a.item_slot);
     __syncthreads();
     if (threadIdx.x == 0) *s_item = (int)atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -1029,10 +1048,9 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
 // its index within the instance; new_inst_ is true when the instance differs
 // from the previous item's (per-instance LDS tables are then reloaded).
 #define PAT_FOR_EACH_ITEM(a)                                              \
-  __shared__ int s_item_;                                                 \
   int prev_inst_ = -1;                                                    \
   for (int iter_ = 0;; ++iter_) {                                         \
-    const int item_ = next_item(a, iter_, &s_item_);                      \
+    const int item_ = next_item(a, iter_);                                \
     if (item_ >= (a).total) break;                                        \
     const int inst_ = __builtin_amdgcn_readfirstlane(find_inst(a, item_)); \
     const bool new_inst_ = inst_ != prev_inst_;                           \
@@ -1043,8 +1061,6 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
 #define PAT_END_ITEM \
   __syncthreads();   \
   }
-
-extern __shared__ __align__(16) unsigned char pat_smem[];
 
 // Two neighbouring complex values (or four reals) as one 16-byte access for
 // float; double values are 16 bytes each already.
@@ -1597,7 +1613,9 @@ __global__ __launch_bounds__(kBlock) void k_line_interp_stream(StageArgs a) {
     if (g + (int)gridDim.x < ngroups) fetch(g + (int)gridDim.x);
     __syncthreads();
     cx<T>* o = out + (size_t)line0 * nz;
-    interp_lines<T, TAPS, true, P2>(I, a, buf, ls, s_ak[k & 1], nl, a.mode, [&](int e, cx<T> v) { o[e] = v; });
+    const double* akk = s_ak[k & 1];
+    interp_lines<T, TAPS, true, P2>(I, a, buf, ls, [&](int b) { return akk[b]; }, nl, a.mode,
+                                    [&](int e, cx<T> v) { o[e] = v; });
   }
 }
 
@@ -1626,10 +1644,11 @@ __global__ __launch_bounds__(kBlock) void k_line_interp(StageArgs a) {
   __syncthreads();
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
   if (pairs) {
-    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, buf, ls, s_ak, nl, a.mode,
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, buf, ls, [&](int b) { return s_ak[b]; }, nl, a.mode,
                                                      [&](int e, cx<T> v) { out[e] = v; });
   } else {
-    interp_lines<T, 0, false, P2>(I, a, buf, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { out[e] = v; });
+    interp_lines<T, 0, false, P2>(I, a, buf, ls, [&](int b) { return s_ak[b]; }, nl, a.mode,
+                                  [&](int e, cx<T> v) { out[e] = v; });
   }
   PAT_END_ITEM
 }
@@ -1660,15 +1679,16 @@ __global__ __launch_bounds__(kBlock) void k_line_spread(StageArgs a) {
 template <typename T, int RS, int TAPS>
 __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   constexpr bool P2 = RS == 0;
-  __shared__ double s_ak[16];
   PAT_FOR_EACH_ITEM(a)
   const int m = I.m, nt = I.nt, nz = I.nz;
   const int lpw = I.lpw_f;
   const int line0 = li * lpw;
   const int nl = min(lpw, I.lines - line0);
   const bool pairs = TAPS > 0 && a.pair_ok;
-  const int H = pairs ? TAPS - 1 : 0;
-  const int ls = m + H;
+  // (no halo: the rare windows that run past the end of a line wrap their
+  // taps, which keeps two lines' buffers within 32 KB of LDS)
+  const int ls = m;
+  auto ak = [&](int b) { return line_ak(I, line0 + b); };
   const int sp = m > nz ? m : nz;
   // (twiddles stay in global memory here: an LDS copy costs this kernel a
   // resident workgroup per CU and the strided reads conflict on banks)
@@ -1676,7 +1696,6 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
   cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT output (permuted order), later the depth line
   cx<T>* gn = gp + lpw * sp;                         // grid in natural order, with halo
-  if (threadIdx.x < nl) s_ak[threadIdx.x] = line_ak(I, line0 + threadIdx.x);
   const cx<T>* gin = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nt;
   if constexpr (P2) {
     // the first FFT stage reads the deconvolved, centred samples from memory
@@ -1694,11 +1713,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
       cx<T>* g = gn + b * ls;
       const int k0 = dif_natural_p2(I.fm, blk * R);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int kk = k0 + r * step;
-        g[kk] = v[r];
-        if (kk < H) g[m + kk] = v[r];
-      }
+      for (int r = 0; r < R; ++r) g[k0 + r * step] = v[r];
     });
   } else {
     load_deconv_pad<T, P2>(I, gin, nl, gp);
@@ -1708,27 +1723,38 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
     for (int e = threadIdx.x; e < nl * m; e += kBlock) {
       int b, j;
       divmod<P2>(e, m, &b, &j);
-      const cx<T> v = gp[b * m + permm[j]];
-      gn[b * ls + j] = v;
-      if (j < H) gn[b * ls + m + j] = v;
+      gn[b * ls + j] = gp[b * m + permm[j]];
     }
     __syncthreads();
   }
   cx<T>* fz = gp;  // the permuted grid is no longer needed
   if (pairs) {
-    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2>(I, a, gn, ls, s_ak, nl, a.mode,
-                                                     [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    interp_lines<T, (TAPS > 0 ? TAPS : 2), true, P2, false>(I, a, gn, ls, ak, nl, a.mode,
+                                                            [&](int e, cx<T> v) { fz[e] = cconj(v); });
   } else {
-    interp_lines<T, 0, false, P2>(I, a, gn, ls, s_ak, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    interp_lines<T, 0, false, P2>(I, a, gn, ls, ak, nl, a.mode, [&](int e, cx<T> v) { fz[e] = cconj(v); });
   }
   __syncthreads();
-  fft_lds<T, RS, true>(fz, I.fz, twz, nl, nz, 1);
-  const int32_t* permz = I.perm + I.fz.perm;
   cx<T>* out = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nz;
-  for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
-    int b, j;
-    divmod<P2>(e, nz, &b, &j);
-    out[e] = cconj(fz[b * nz + permz[j]]);
+  if constexpr (P2) {
+    // the last stage stores each output at its natural position: for a given
+    // r, a wave's butterflies cover one contiguous run of the line
+    const int stepz = nz / I.fz.rad[I.fz.nst - 1];
+    fft_lds_p2_sink<T, true>(fz, I.fz, twz, nl, nz, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* o = out + b * nz;
+      const int k0 = dif_natural_p2(I.fz, blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[k0 + r * stepz] = cconj(v[r]);
+    });
+  } else {
+    fft_lds<T, RS, true>(fz, I.fz, twz, nl, nz, 1);
+    const int32_t* permz = I.perm + I.fz.perm;
+    for (int e = threadIdx.x; e < nl * nz; e += kBlock) {
+      int b, j;
+      divmod<P2>(e, nz, &b, &j);
+      out[e] = cconj(fz[b * nz + permz[j]]);
+    }
   }
   PAT_END_ITEM
 }
@@ -1838,6 +1864,10 @@ int resident_blocks(const void* kernel, size_t shmem) {
 template <typename K>
 hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st, StageTimer* tm) {
   if (a.total <= 0) return hipSuccess;
+  if (a.counter) {
+    a.item_slot = (int32_t)((shmem + 15) & ~(size_t)15);
+    shmem = (size_t)a.item_slot + 16;
+  }
   if (shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);

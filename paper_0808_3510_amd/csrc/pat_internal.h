@@ -101,10 +101,11 @@ inline size_t lds_spread_lists(int nz, int taps, size_t cs) {
 }
 inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, cs); }
 // fused type-2 line kernel: lpw_f lines of max(m, nz) (FFT scratch, then the
-// depth line) and lpw_f grid lines of m + taps (natural order with halo)
+// depth line) and lpw_f grid lines of m (natural order, no halo: at 1024
+// points two lines take exactly 32 KB, five workgroups per compute unit)
 inline size_t lds_fused2(const Inst& I, size_t cs) {
   const size_t sp = (size_t)(I.m > I.nz ? I.m : I.nz);
-  return (size_t)I.lpw_f * (sp + (size_t)I.m + I.taps) * cs;
+  return (size_t)I.lpw_f * (sp + (size_t)I.m) * cs;
 }
 // fused type-1 line kernel: a region of max(m, lpw_a nz) (the depth FFTs,
 // then one grid line), lpw_a depth spectra in natural order, the lists
