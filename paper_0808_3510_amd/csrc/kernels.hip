@@ -1298,6 +1298,148 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   PAT_END_ITEM
 }
 
+// k_tr_x1_r2c as a software pipeline (see k_tr_x2_pipe), for one instance
+// without a cut-off on this pass, len a multiple of 4, tb even and
+// n1 * tb / 2 <= kPipeU * kBlock four-sample loads per tile.
+template <typename T, int RS>
+__global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a);
+
+// k_tr_x2 as a software pipeline for one instance whose tile is at most
+// kPipeU column pairs per thread (n2 * tb / 2 <= kPipeU * kBlock, tb even): a
+// persistent grid strides over the tiles, and each workgroup issues the
+// loads of its next tile into registers right after storing the current one
+// into LDS, so they are in flight while the current tile is transformed and
+// written back.  The output positions sit in LDS beside the twiddles (a
+// table read from memory in the store loop would wait for those loads).
+constexpr int kPipeU = 8;
+template <typename T, int RS>
+__global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
+  const Inst& I = *a.inst[0];
+  const int L = I.n2;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
+  cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
+  load_twiddles(tw, I, I.f2);
+  const int32_t* perm = I.perm + I.f2.perm;
+  for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
+  const int len = a.len_nz ? I.nz : I.nt;
+  const int tb = I.tb, hb = tb / 2;
+  const int ntile = (len + tb - 1) / tb;
+  const bool inv = a.mode != 0;
+  cx<T>* base = static_cast<cx<T>*>(a.out[0]);
+  cx<T> pre[2 * kPipeU];
+  auto fetch = [&](int item) {
+    const int k1 = item / ntile;
+    const int t0 = (item - k1 * ntile) * tb;
+    const cx<T>* io = base + (size_t)k1 * L * len + t0;
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      pre[2 * u] = pre[2 * u + 1] = mk(T(0), T(0));
+      if (e < L * hb) {
+        int x, c;
+        divmod<true>(e, hb, &x, &c);
+        if (t0 + 2 * c < len) ld_pair(io + (size_t)x * len + 2 * c, &pre[2 * u], &pre[2 * u + 1]);
+      }
+    }
+  };
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      if (e < L * hb) {
+        buf[2 * e] = inv ? cconj(pre[2 * u]) : pre[2 * u];
+        buf[2 * e + 1] = inv ? cconj(pre[2 * u + 1]) : pre[2 * u + 1];
+      }
+    }
+    __syncthreads();
+    const int k1 = item / ntile;
+    const int t0 = (item - k1 * ntile) * tb;
+    cx<T>* io = base + (size_t)k1 * L * len + t0;
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    fft_lds<T, RS, false>(buf, I.f2, tw, tb, 1, tb);
+    for (int e = threadIdx.x; e < L * hb; e += kBlock) {
+      int kk, c;
+      divmod<true>(e, hb, &kk, &c);
+      if (t0 + 2 * c < len) {
+        const cx<T>* s = buf + pos[kk] * tb + 2 * c;
+        st_pair(io + (size_t)kk * len + 2 * c, inv ? cconj(s[0]) : s[0], inv ? cconj(s[1]) : s[1]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int RS>
+__global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a) {
+  constexpr bool P2 = RS == 0;
+  const Inst& I = *a.inst[0];
+  const int L = I.n1;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
+  cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
+  load_twiddles(tw, I, I.f1);
+  const int32_t* perm = I.perm + I.f1.perm;
+  for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
+  const int len = a.len_nz ? I.nz : I.nt;
+  const int tb = I.tb, hb = tb / 2;
+  const int ntile = (len + 2 * tb - 1) / (2 * tb);
+  const size_t rstride = (size_t)I.n2 * len;
+  const T* in = static_cast<const T*>(a.in[0]);
+  cx<T>* out = static_cast<cx<T>*>(a.out[0]);
+  cx<T> pre[2 * kPipeU];
+  auto fetch = [&](int item) {
+    const int x2 = item / ntile;
+    const int t0 = (item - x2 * ntile) * 2 * tb;
+    const T* in0 = in + (size_t)x2 * len + t0;
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      pre[2 * u] = pre[2 * u + 1] = mk(T(0), T(0));
+      if (e < L * hb) {
+        int x, c;
+        divmod<true>(e, hb, &x, &c);
+        if (t0 + 4 * c < len)
+          ld_pair<T, true>(reinterpret_cast<const cx<T>*>(in0 + x * rstride + 4 * c), &pre[2 * u], &pre[2 * u + 1]);
+      }
+    }
+  };
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < kPipeU; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      if (e < L * hb) {
+        buf[2 * e] = pre[2 * u];
+        buf[2 * e + 1] = pre[2 * u + 1];
+      }
+    }
+    __syncthreads();
+    const int x2 = item / ntile;
+    const int t0 = (item - x2 * ntile) * 2 * tb;
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
+    cx<T>* out0 = out + (size_t)x2 * len + t0;
+    for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
+      int kk, b;
+      divmod<true>(e, tb, &kk, &b);
+      if (t0 + 2 * b >= len) continue;
+      const int kn = kk == 0 ? 0 : L - kk;
+      const cx<T> z = buf[pos[kk] * tb + b];
+      const cx<T> zn = cconj(buf[pos[kn] * tb + b]);
+      const T h = T(0.5);
+      const cx<T> pa = cscl(cadd(z, zn), h);
+      const cx<T> d = csub(z, zn);
+      const cx<T> pb = mk(h * d.y, -h * d.x);
+      st_pair(out0 + (size_t)kk * rstride + 2 * b, pa, pb);
+    }
+    __syncthreads();
+  }
+}
+
 // Inverse DFT over the first axis from bins 0..n1/2 (the others are the
 // complex conjugates of their mirror bins), real part.  Two neighbouring
 // samples are transformed together: Z = X_a + i X_b inverts to x_a + i x_b.
@@ -1377,6 +1519,80 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
     }
   }
   PAT_END_ITEM
+}
+
+// k_tr_c2r_k1 as a software pipeline (see k_tr_x2_pipe), for one instance
+// without a cut-off on this pass, len a multiple of 4, tb even and
+// n1 * tb <= 2 kPipeU * kBlock bins per tile.
+template <typename T, int RS>
+__global__ __launch_bounds__(kBlock) void k_tr_c2r_pipe(StageArgs a) {
+  const Inst& I = *a.inst[0];
+  const int L = I.n1, half = L / 2;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
+  int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
+  cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
+  load_twiddles(tw, I, I.f1);
+  const int32_t* perm = I.perm + I.f1.perm;
+  for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
+  const int len = a.len_nz ? I.nz : I.nt;
+  const int tb = I.tb, hb = tb / 2;
+  const int ntile = (len + 2 * tb - 1) / (2 * tb);
+  const size_t rstride = (size_t)I.n2 * len;
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
+  T* out = static_cast<T*>(a.out[0]);
+  constexpr int U = 2 * kPipeU;
+  cx<T> pre[U];
+  auto fetch = [&](int item) {
+    const int x2 = item / ntile;
+    const int t0 = (item - x2 * ntile) * 2 * tb;
+    const cx<T>* in0 = in + (size_t)x2 * len + t0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      pre[u] = mk(T(0), T(0));
+      if (e < L * tb) {
+        int kk, b;
+        divmod<true>(e, tb, &kk, &b);
+        const int src = kk <= half ? kk : L - kk;
+        cx<T> xa = mk(T(0), T(0)), xb = mk(T(0), T(0));
+        if (t0 + 2 * b < len) ld_pair(in0 + (size_t)src * rstride + 2 * b, &xa, &xb);
+        if (kk == 0 || kk == half) {
+          xa.y = T(0);
+          xb.y = T(0);
+        } else if (kk > half) {
+          xa = cconj(xa);
+          xb = cconj(xb);
+        }
+        // Z = xa + i xb, stored conjugated (inverse DFT as conj(FFT(conj(.))))
+        pre[u] = mk(xa.x - xb.y, -(xa.y + xb.x));
+      }
+    }
+  };
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      if (e < L * tb) buf[e] = pre[u];
+    }
+    __syncthreads();
+    const int x2 = item / ntile;
+    const int t0 = (item - x2 * ntile) * 2 * tb;
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
+    T* out0 = out + (size_t)x2 * len + t0;
+    for (int e = threadIdx.x; e < L * hb; e += kBlock) {
+      int x, c;
+      divmod<true>(e, hb, &x, &c);
+      if (t0 + 4 * c < len) {
+        const cx<T>* y = buf + pos[x] * tb + 2 * c;  // conj of x_a + i x_b
+        st_pair<T, true>(reinterpret_cast<cx<T>*>(out0 + (size_t)x * rstride + 4 * c), mk(y[0].x, -y[0].y),
+                         mk(y[1].x, -y[1].y));
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1988,16 +2204,33 @@ struct Runner {
 
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
+    const int len = nz ? h[0].nz : h[0].nt;
+    if (sizeof(T) == 4 && n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
+        h[0].n1 * (h[0].tb / 2) <= kPipeU * kBlock) {
+      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
+      return launch_persistent(k_tr_x1_pipe<T, RS>, "dft_x1", a, shm, st, tm);
+    }
     return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
                   tm);
   }
   hipError_t x2(void* const* io, bool nz, int inv) {
     StageArgs a = base(IT_X2, nz, inv, io, io);
+    // (float only: the double registers of a prefetched tile halve occupancy)
+    if (sizeof(T) == 4 && n == 1 && !a.counter && h[0].tb % 2 == 0 && h[0].n2 * (h[0].tb / 2) <= kPipeU * kBlock) {
+      const size_t shm = lds_tile_x2(h[0], cs) + (size_t)((h[0].n2 + 3) & ~3) * sizeof(int32_t);
+      return launch_persistent(k_tr_x2_pipe<T, RS>, inv ? "idft_x2" : "dft_x2", a, shm, st, tm);
+    }
     return launch(k_tr_x2<T, RS>, inv ? "idft_x2" : "dft_x2", a,
                   max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
   }
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_C2R, nz, 0, in, out);
+    const int len = nz ? h[0].nz : h[0].nt;
+    if (sizeof(T) == 4 && n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
+        h[0].n1 * h[0].tb <= 2 * kPipeU * kBlock) {
+      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
+      return launch_persistent(k_tr_c2r_pipe<T, RS>, "idft_x1_c2r", a, shm, st, tm);
+    }
     return launch(k_tr_c2r_k1<T, RS>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
                   st, tm);
   }
