@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -308,12 +309,12 @@ def cpu_baseline(p_np, g, f_gpu, budget_s, np):
 
 
 KERNEL_OF_STAGE = {
-    # library stage name -> kernel symbol prefix in the profiler's output
-    "nufft_fused": "void pat::k_line_nufft2<",
-    "nufft_adjoint_fused": "void pat::k_line_nufft1<",
-    "dft_x1": "void pat::k_tr_x1_r2c<",
-    "dft_x2": "void pat::k_tr_x2<",
-    "idft_x1_c2r": "void pat::k_tr_c2r_k1<",
+    # library stage name -> kernel symbol prefixes in the profiler's output
+    "nufft_fused": ("void pat::k_line_nufft2<",),
+    "nufft_adjoint_fused": ("void pat::k_line_nufft1<",),
+    "dft_x1": ("void pat::k_tr_x1_r2c<", "void pat::k_tr_x1_pipe<"),
+    "dft_x2": ("void pat::k_tr_x2<", "void pat::k_tr_x2_pipe<"),
+    "idft_x1_c2r": ("void pat::k_tr_c2r_k1<", "void pat::k_tr_c2r_pipe<"),
 }
 
 
@@ -326,50 +327,54 @@ def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision)
     profiles/traffic.json with the hash of the kernel sources it belongs to."""
     import csv
 
-    def per_kernel(path, counter):
-        acc = {}
+    def per_dispatch(path, counter):
+        # counter value of each dispatch (summed over the GPU's blocks)
+        acc, name_grid = {}, {}
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] != counter:
                     continue
-                key = (r["Kernel_Name"], int(r["Grid_Size"]), r.get("Dispatch_Id", r.get("Correlation_Id", "")))
-                acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
-        by_name = {}
-        for (name, grid, _), v in acc.items():
-            by_name.setdefault((name, grid), []).append(v)
-        return by_name
+                d = int(r.get("Dispatch_Id", r.get("Correlation_Id", "0")))
+                acc[d] = acc.get(d, 0.0) + float(r["Counter_Value"])
+                name_grid[d] = (r["Kernel_Name"], int(r["Grid_Size"]))
+        return acc, name_grid
 
-    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
-    write = per_kernel(write_csv, "WRITE_SIZE")
+    fetch, fnames = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, wnames = per_dispatch(write_csv, "WRITE_SIZE")
 
-    def largest(d, pred):
+    def largest(vals, names, pred):
         # the largest copy/fill dispatch (the calibration one)
         best = None
-        for (name, _), vals in d.items():
-            if pred(name):
-                v = max(vals)
-                best = v if best is None or v > best else best
+        for d, v in vals.items():
+            if pred(names[d][0]) and (best is None or v > best):
+                best = v
         return best
 
     kib = copy_bytes / 1024.0
-    f_copy = largest(fetch, lambda n: "copy" in n.lower() or "elementwise" in n.lower())
-    w_fill = largest(write, lambda n: "fill" in n.lower() or "elementwise" in n.lower())
+    f_copy = largest(fetch, fnames, lambda n: "copy" in n.lower() or "elementwise" in n.lower())
+    w_fill = largest(write, wnames, lambda n: "fill" in n.lower() or "elementwise" in n.lower())
     f_scale, w_scale = kib / f_copy, kib / w_fill
     out = {"kernel_source": kernel_source_hash(), "copy_bytes": copy_bytes,
            "fetch_scale": f_scale, "write_scale": w_scale, "bytes_per_launch": {}, "raw_kib_per_launch": {}}
-    # one entry per stage and launch size (a kernel serves several stages and
-    # both R and R^T); the key carries the grid size when a stage has several
-    for stage, prefix in KERNEL_OF_STAGE.items():
-        grids = sorted({g for (n, g) in fetch if n.startswith(prefix)})
-        for g in grids:
-            fv = [v for (n, gg), vs in fetch.items() if n.startswith(prefix) and gg == g for v in vs]
-            wv = [v for (n, gg), vs in write.items() if n.startswith(prefix) and gg == g for v in vs]
-            if not fv or not wv:
+    # The two runs make the same dispatches, so FETCH and WRITE pair by
+    # dispatch id.  A stage's dispatches are grouped by kernel, grid and size
+    # class (the transverse kernels serve R and R^T on lines of nt and of nz
+    # samples; their persistent forms launch the same grid for both), and the
+    # key carries the group when a stage has several.
+    for stage, prefixes in KERNEL_OF_STAGE.items():
+        groups = {}
+        for d, (name, grid) in fnames.items():
+            if d not in write or not name.startswith(prefixes):
                 continue
-            f_avg, w_avg = sum(fv) / len(fv), sum(wv) / len(wv)
-            key = f"{stage}:{workload}:{precision}" + (f"[grid={g}]" if len(grids) > 1 else "")
-            out["raw_kib_per_launch"][key] = {"fetch": f_avg, "write": w_avg, "dispatches": [len(fv), len(wv)],
-                                              "grid_threads": g}
+            size_class = int(round(math.log2(max(fetch[d], 1.0))))
+            groups.setdefault((name, grid, size_class), []).append(d)
+        for (name, grid, sc), ds in sorted(groups.items(), key=lambda kv: (kv[0][2], kv[0][1])):
+            f_avg = sum(fetch[d] for d in ds) / len(ds)
+            w_avg = sum(write[d] for d in ds) / len(ds)
+            key = f"{stage}:{workload}:{precision}" + (f"[{name.split('<')[0].split('::')[-1]},grid={grid},"
+                                                       f"class={sc}]" if len(groups) > 1 else "")
+            out["raw_kib_per_launch"][key] = {"fetch": f_avg, "write": w_avg, "dispatches": len(ds),
+                                              "grid_threads": grid, "kernel": name}
             out["bytes_per_launch"][key] = 1024.0 * (f_avg * f_scale + w_avg * w_scale)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
