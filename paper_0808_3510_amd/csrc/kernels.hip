@@ -1975,6 +1975,104 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft2(StageArgs a) {
   PAT_END_ITEM
 }
 
+// k_line_nufft2 as a software pipeline for one FP32 instance with c = 2
+// (m = 2 nt), power-of-two lengths, a first radix of 8 and exactly one
+// first-stage butterfly per thread ((m / 8) lpw_f = kBlock).  With c = 2 and
+// the centred padding, butterfly j of a line takes the samples j, j + nt/4,
+// j + nt/2 and j + 3nt/4 (the other four inputs are zeros).  A persistent grid
+// strides over the line groups; each workgroup loads its next group's
+// samples into registers before the last stage of the oversampled FFT, so
+// they are in flight through that stage and the interpolation, which load
+// nothing else from memory.  The deconvolution factors and the first-stage
+// twiddle of a thread are the same for every group and are read once.
+template <typename T, int TAPS>
+__global__ __launch_bounds__(kBlock, 5) void k_line_nufft2_pipe(StageArgs a) {
+  const Inst& I = *a.inst[0];
+  const int m = I.m, nt = I.nt, nz = I.nz, lpw = I.lpw_f;
+  const int sub = m >> 3, lsub = __builtin_ctz((unsigned)sub);
+  const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT scratch, later the depth lines
+  cx<T>* gn = gp + lpw * m;                          // grid lines in natural order
+  const T* sn = static_cast<const T*>(I.sn);
+  const int q = nt >> 2;
+  // inputs r = 0, 1, 6, 7 of the butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
+  const int ns[4] = {j + 2 * q, j + 3 * q, j, j + q};
+  T snr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) snr[i] = sn[ns[i]];
+  const cx<T> w1 = twm[j];
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
+  cx<T>* outb = static_cast<cx<T>*>(a.out[0]);
+  cx<T> pre[4];
+  auto fetch = [&](int item) {
+    const int line0 = item * lpw;
+    const bool ok = line0 + bb < I.lines;
+    const cx<T>* gin = in + (size_t)(line0 + bb) * nt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pre[i] = ok ? gin[ns[i]] : mk(T(0), T(0));
+  };
+  const int step = m / I.fm.rad[I.fm.nst - 1];
+  const int stepz = nz / I.fz.rad[I.fz.nst - 1];
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+    const int line0 = item * lpw;
+    const int nl = min(lpw, I.lines - line0);
+    {
+      cx<T> v[8];
+      v[0] = cscl(pre[0], snr[0]);
+      v[1] = cscl(pre[1], snr[1]);
+      v[2] = v[3] = v[4] = v[5] = mk(T(0), T(0));
+      v[6] = cscl(pre[2], snr[2]);
+      v[7] = cscl(pre[3], snr[3]);
+      dft_pow2<T, 8>(v);
+      twiddle_pow2<T, 8>(v, w1);
+      cx<T>* p = gp + bb * m + j;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) p[r * sub] = v[r];
+    }
+    __syncthreads();
+    int Li = sub;
+    for (int s = 1; s + 1 < I.fm.nst; ++s) {
+      const int R = I.fm.rad[s];
+      if (R == 8) fft_stage<T, 8, true, true>(gp, Li, m, twm, lpw, m, 1);
+      else if (R == 4) fft_stage<T, 4, true, true>(gp, Li, m, twm, lpw, m, 1);
+      else fft_stage<T, 2, true, true>(gp, Li, m, twm, lpw, m, 1);
+      __syncthreads();
+      Li /= R;
+    }
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    auto sink = [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* g = gn + b * m;
+      const int k0 = dif_natural_p2(I.fm, blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) g[k0 + r * step] = v[r];
+    };
+    {
+      const int R = I.fm.rad[I.fm.nst - 1];
+      if (R == 8) fft_last_stage_p2<T, 8, true>(gp, m, lpw, m, 1, sink);
+      else if (R == 4) fft_last_stage_p2<T, 4, true>(gp, m, lpw, m, 1, sink);
+      else fft_last_stage_p2<T, 2, true>(gp, m, lpw, m, 1, sink);
+    }
+    __syncthreads();
+    cx<T>* fz = gp;
+    interp_lines<T, TAPS, true, true, false>(I, a, gn, m, [&](int b) { return line_ak(I, line0 + b); }, nl, a.mode,
+                                             [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    __syncthreads();
+    cx<T>* out = outb + (size_t)line0 * nz;
+    fft_lds_p2_sink<T, true>(fz, I.fz, twz, nl, nz, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* o = out + b * nz;
+      const int k0 = dif_natural_p2(I.fz, blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[k0 + r * stepz] = cconj(v[r]);
+    });
+  }
+}
+
 // Fused depth DFT + spreading + transposed a2 (operators R^T and A).  A work
 // item holds lpw_a lines: their depth DFTs run together (power-of-two
 // builds: the first stage reads the spectra from memory and the last writes
@@ -2275,6 +2373,12 @@ struct Runner {
   }
   hipError_t nufft2(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LF, true, mode, in, out);
+    if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
+      const Inst& I = h[0];
+      if (n == 1 && !a.counter && a.pair_ok && I.m == 2 * I.nt && I.m >= I.nz && I.fm.nst >= 2 &&
+          I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock)
+        return launch_persistent(k_line_nufft2_pipe<T, TAPS>, "nufft_fused", a, lds_fused2(I, cs), st, tm);
+    }
     return launch(k_line_nufft2<T, RS, TAPS>, "nufft_fused", a,
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
