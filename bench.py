@@ -310,7 +310,7 @@ def cpu_baseline(p_np, g, f_gpu, budget_s, np):
 
 KERNEL_OF_STAGE = {
     # library stage name -> kernel symbol prefixes in the profiler's output
-    "nufft_fused": ("void pat::k_line_nufft2<",),
+    "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<"),
     "nufft_adjoint_fused": ("void pat::k_line_nufft1<",),
     "dft_x1": ("void pat::k_tr_x1_r2c<", "void pat::k_tr_x1_pipe<"),
     "dft_x2": ("void pat::k_tr_x2<", "void pat::k_tr_x2_pipe<"),
