@@ -159,3 +159,25 @@ def test_spread_lines_is_adjoint_of_interp_lines(prec):
     a = torch.vdot(Vd.flatten(), NU.flatten()).item()   # <V, N U>
     b = torch.vdot(NhV.flatten().to(cdt), Uc.flatten()).item()  # <N^H V, U>
     assert abs(a - b) <= tol * abs(a)
+
+
+@pytest.mark.parametrize("g", [
+    geo(32, 32, 64, 32, 1 / 32, 1 / 32, 1 / 32),   # fused and transverse pipelines
+    geo(64, 64, 128, 64, 1.0, 0.9, 1.1),           # fused pipeline, three-stage FFTs
+    geo(32, 1, 64, 32),                            # 2D: 17 lines, a short last group
+    geo(24, 20, 48, 24, 1.0, 0.8, 1.2),            # transverse pipelines, general radices
+])
+def test_pipelined_kernels_match_one_tile_kernels(g):
+    """A single FP32 plan runs the software-pipelined persistent kernels; the
+    same plan in a batched call runs the one-tile-per-workgroup kernels with a
+    work queue.  Both against each other and against the oracle."""
+    say(f"pipelined vs one-tile {g}")
+    p = inputs.random_array((g["n1"], g["n2"], g["nt"]), 700)
+    plan = make_plan(g, "f32")
+    P = to_dev(p, "f32")
+    a = plan.reconstruct(P).clone()
+    outs, _ = pat.reconstruct_batched([plan], [P])
+    torch.cuda.synchronize()
+    b = outs[0]
+    assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() < 1e-6
+    assert relerr(a.cpu().double().numpy(), recon.reconstruct(p, g)) < TOL["f32"]
