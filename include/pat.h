@@ -46,7 +46,7 @@ extern "C" {
 typedef enum {
   PAT_OK = 0,
   PAT_ERR_INVALID_ARG = 1, /* null/misaligned pointer, bad geometry value */
-  PAT_ERR_UNSUPPORTED = 2, /* valid but outside what this build supports */
+  PAT_ERR_UNSUPPORTED = 2, /* valid but outside what the library supports */
   PAT_ERR_WORKSPACE = 3,   /* table not uploaded / workspace missing */
   PAT_ERR_HIP = 4,         /* a HIP runtime call failed */
   PAT_ERR_INTERNAL = 5

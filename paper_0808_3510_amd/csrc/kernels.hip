@@ -4,10 +4,12 @@
 // workgroup or from a device work counter drained by a persistent grid (the
 // batched form).
 //
-// Stages (see pat.h for the operators they compose):
+// Stages (a1 .. a5 are the steps of R as pat.h lists them under
+// pat_reconstruct; see pat.h for the operators they compose):
 //   k_tr_x1_r2c   DFT over the first detector axis, real input, half spectrum
 //   k_tr_x2       DFT over the second detector axis (either direction)
 //   k_tr_c2r_k1   inverse DFT over the first axis from the half spectrum, real part
+//   k_tr_*_pipe   the three above as software pipelines (one FP32 instance)
 //   k_line_fft    DFT along contiguous lines (depth axis)
 //   k_line_a2     deconvolve by 1/Psi, centre, zero-pad to c*nt, FFT (eq. nufft-c)
 //   k_line_a2t    its transpose: inverse FFT, pick, multiply by 1/Psi
@@ -16,6 +18,7 @@
 //   k_line_spread its transpose (type-1), gathered per grid cell over the
 //                 monotone node list of the line: no atomics, deterministic
 //   k_line_nufft2 a2 + a3 + inverse depth DFT fused per line group in LDS
+//                 (k_line_nufft2_pipe: its software pipeline for c = 2)
 //   k_line_nufft1 depth DFT + spreading + transposed a2 fused per line in LDS
 // The fused kernels never store the oversampled grid; the staged ones do
 // (bf16 grid option, and the stand-alone a3 / spreading entry points).
