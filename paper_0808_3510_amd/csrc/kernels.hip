@@ -1776,10 +1776,10 @@ struct GridChunk<float, bf2> {
 // workgroup walks line groups (lpw_i lines) with stride gridDim.x; the next
 // group's grid is loaded into registers (16-byte loads) before the current
 // group is interpolated, so each workgroup keeps its memory requests in
-// flight while it computes.  Two LDS buffers of lpw_i lines (each with a
-// halo of TAPS - 1 and a stride rounded to 16 bytes) alternate; one barrier
-// per group suffices because a buffer is refilled only after the following
-// group's barrier, which every thread reaches after its last read of it.
+// flight while it computes.  One LDS buffer of lpw_i lines (with a halo of
+// TAPS - 1 and a stride rounded to 16 bytes), refilled after a barrier that
+// follows the interpolation: half the LDS of a double buffer, so one more
+// workgroup fits a compute unit, which is worth the extra barrier.
 template <typename T, typename G, int TAPS, bool P2, int NPRE>
 __global__ __launch_bounds__(kBlock) void k_line_interp_stream(StageArgs a) {
   using C = GridChunk<T, G>;
@@ -1809,7 +1809,7 @@ __global__ __launch_bounds__(kBlock) void k_line_interp_stream(StageArgs a) {
   if (g >= ngroups) return;
   fetch(g);
   for (int k = 0; g < ngroups; g += gridDim.x, ++k) {
-    cx<T>* buf = bufs + (k & 1) * lpw * ls;
+    cx<T>* buf = bufs;
     const int line0 = g * lpw;
     const int nl = min(lpw, lines - line0);
     const int nch = nl * m / EPC;
@@ -1835,6 +1835,7 @@ __global__ __launch_bounds__(kBlock) void k_line_interp_stream(StageArgs a) {
     const double* akk = s_ak[k & 1];
     interp_lines<T, TAPS, true, P2>(I, a, buf, ls, [&](int b) { return akk[b]; }, nl, a.mode,
                                     [&](int e, cx<T> v) { o[e] = v; });
+    __syncthreads();  // every read of the buffer is done before it is refilled
   }
 }
 

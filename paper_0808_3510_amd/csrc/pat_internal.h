@@ -86,12 +86,12 @@ inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.nz * (I.lp
 inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.m * (I.lpw_m + 1) * cs; }
 // interp: lpw_i grid lines of m entries plus a halo of taps - 1
 inline size_t lds_interp(const Inst& I, size_t cs) { return (size_t)I.lpw_i * ((size_t)I.m + I.taps) * cs; }
-// streamed interp: two buffers of lpw_i lines, line stride m + taps - 1
+// streamed interp: one buffer of lpw_i lines, line stride m + taps - 1
 // rounded up to 16 bytes
 inline size_t lds_interp_stream(const Inst& I, size_t cs) {
   const size_t q = cs >= 16 ? 1 : 16 / cs;
   const size_t ls = ((size_t)I.m + I.taps - 1 + q - 1) / q * q;
-  return 2 * (size_t)I.lpw_i * ls * cs;
+  return (size_t)I.lpw_i * ls * cs;
 }
 // spreading lists: per-node value, zero-padded tap-weight row (taps + 6
 // entries, made odd), first tap; nz + 2 nodes at most
