@@ -874,12 +874,14 @@ __device__ __forceinline__ void interp_lines(const Inst& I, const StageArgs& a, 
 //   mode 1 (A): nodes -nu+(nz/2 .. 0), +nu+(0 .. nz/2); value
 //     (scale / 2) exp(i pi nu) (F_l + F_-l) (single term at l = 0, -nz/2).
 // fget(l_index) reads the depth spectrum, put(j, value) receives cell j and
-// put4(j, values) the four cells j .. j + 3 (j a multiple of 4).
-template <typename T>
+// putk(j, values) the KC cells j .. j + KC - 1 (j a multiple of KC).
+// KC = 4 in the stand-alone kernel (16-byte stores); the fused adjoint
+// kernel takes KC = 2, whose shorter weight rows keep its LDS within 32 KB.
+template <typename T, int KC = 4>
 struct SpreadLds {
   // a thread gathers kCells consecutive cells; kPad zeros on both sides of a
   // weight row let it read kCells weights of any node in range without tests
-  static constexpr int kCells = 4;
+  static constexpr int kCells = KC;
   static constexpr int kPad = kCells - 1;
   static __host__ __device__ constexpr int row(int taps) { return (taps + 2 * kPad) | 1; }
   cx<T>* val;  // [node] value
@@ -896,10 +898,10 @@ struct SpreadLds {
 };
 
 // First tap and weight row of node i at nu.
-template <typename T, int TAPS, bool PAIRS>
-__device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, double nu, SpreadLds<T> L, int i,
+template <typename T, int TAPS, bool PAIRS, int KC>
+__device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, double nu, SpreadLds<T, KC> L, int i,
                                             int taps, int rw) {
-  constexpr int P = SpreadLds<T>::kPad;
+  constexpr int P = SpreadLds<T, KC>::kPad;
   const double xc = I.c * nu;
   const double f = floor(xc - I.ck);
   const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
@@ -918,8 +920,8 @@ __device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, d
   }
 }
 
-template <typename T, int TAPS, bool PAIRS, typename Fget, typename Put, typename Put4>
-__device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, int line, int mode, SpreadLds<T> L,
+template <typename T, int TAPS, bool PAIRS, int KC, typename Fget, typename Put, typename Put4>
+__device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, int line, int mode, SpreadLds<T, KC> L,
                                             Fget fget, Put put, Put4 put4) {
   const int m = I.m, nz = I.nz, half = nz / 2, taps = PAIRS ? TAPS : I.taps;
   const int q0 = mode == 0 ? 1 : 0;  // smallest |l| listed
@@ -927,7 +929,7 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
   const int nn = 2 * nq;             // nodes
   const double Ak = line_ak(I, line);
   const double wsc = I.wcoef * I.scale;
-  const int rw = SpreadLds<T>::row(taps);
+  const int rw = SpreadLds<T, KC>::row(taps);
   for (int i = threadIdx.x; i < nn; i += kBlock) {
     // node i: +nu+(q0 + i - nq) for i >= nq, else -nu+(q0 + nq - 1 - i)
     const bool pos = i >= nq;
@@ -948,7 +950,7 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
     // conjugate
     const cx<T> ph = phase_mpi<T>(nup);
     L.val[i] = cscl(cmul(q, pos ? cconj(ph) : ph), T(cf));
-    spread_node<T, TAPS, PAIRS>(I, a, pos ? nup : -nup, L, i, taps, rw);
+    spread_node<T, TAPS, PAIRS, KC>(I, a, pos ? nup : -nup, L, i, taps, rw);
   }
   __syncthreads();
   const int jlo = L.j0s[0];
@@ -987,8 +989,8 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
   // have first taps in [v - taps + 1, v + kCells - 1]: one contiguous node
   // range.  Node i adds weight (v + c - (j0 - jlo)) times its value to cell
   // c; the padded weight row makes out-of-window taps read zeros.
-  constexpr int kCells = SpreadLds<T>::kCells;
-  constexpr int P = SpreadLds<T>::kPad;
+  constexpr int kCells = SpreadLds<T, KC>::kCells;
+  constexpr int P = SpreadLds<T, KC>::kPad;
   const int vend = span + taps - 1;
   for (int j = kCells * (int)threadIdx.x; j < m; j += kCells * kBlock) {
     cx<T> acc[kCells];
@@ -2095,7 +2097,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   const int sg = m > lpw * nz ? m : lpw * nz;
   cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // depth-FFT scratch, then one grid line
   cx<T>* qn = grid + sg;                              // lpw depth spectra, natural order
-  const SpreadLds<T> L = SpreadLds<T>::carve(qn + lpw * nz, nz, I.taps);
+  const SpreadLds<T, 2> L = SpreadLds<T, 2>::carve(qn + lpw * nz, nz, I.taps);
   const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nz;
   if constexpr (P2) {
     const int stepz = nz / I.fz.rad[I.fz.nst - 1];  // weight of the last digit in k
@@ -2123,7 +2125,7 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
   auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
   auto put4 = [&](int j, const cx<T>* v) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) grid[j + c] = cconj(v[c]);
+    for (int c = 0; c < 2; ++c) grid[j + c] = cconj(v[c]);
   };
   for (int b = 0; b < nl; ++b) {
     // (spread_line's first barrier also ends every read of the previous

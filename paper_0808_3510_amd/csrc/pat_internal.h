@@ -95,11 +95,13 @@ inline size_t lds_interp_stream(const Inst& I, size_t cs) {
 }
 // spreading lists: per-node value, zero-padded tap-weight row (taps + 6
 // entries, made odd), first tap; nz + 2 nodes at most
-inline size_t lds_spread_lists(int nz, int taps, size_t cs) {
-  const size_t row = (size_t)((taps + 6) | 1);
+inline size_t lds_spread_lists(int nz, int taps, size_t cs, int kcells = 4) {
+  const size_t row = (size_t)((taps + 2 * (kcells - 1)) | 1);
   return ((size_t)nz + 2) * (cs + row * (cs / 2) + sizeof(int32_t));
 }
+// stand-alone spreading gathers 4 cells per thread, the fused adjoint 2
 inline size_t lds_spread(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, cs); }
+inline size_t lds_spread_fused(const Inst& I, size_t cs) { return lds_spread_lists(I.nz, I.taps, cs, 2); }
 // fused type-2 line kernel: lpw_f lines of max(m, nz) (FFT scratch, then the
 // depth line) and lpw_f grid lines of m (natural order, no halo: at 1024
 // points two lines take exactly 32 KB, five workgroups per compute unit)
@@ -111,7 +113,7 @@ inline size_t lds_fused2(const Inst& I, size_t cs) {
 // then one grid line), lpw_a depth spectra in natural order, the lists
 inline size_t lds_fused1(const Inst& I, size_t cs) {
   const size_t za = (size_t)I.lpw_a * I.nz;
-  return ((size_t)I.m > za ? (size_t)I.m : za) * cs + za * cs + lds_spread(I, cs);
+  return ((size_t)I.m > za ? (size_t)I.m : za) * cs + za * cs + lds_spread_fused(I, cs);
 }
 
 }  // namespace pat

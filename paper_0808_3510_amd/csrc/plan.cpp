@@ -421,7 +421,8 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   // the adjoint kernel transforms lpw_a depth lines together (power-of-two
   // builds), then spreads them one by one
   I.lpw_a = I.pow2 ? clampi(m / g.nz, 1, 8) : 1;
-  while (I.lpw_a > 1 && lds_fused1(I, cs) > 48 * 1024) I.lpw_a /= 2;
+  // (down to 32 KB of LDS: five workgroups per compute unit)
+  while (I.lpw_a > 1 && lds_fused1(I, cs) > 32 * 1024) I.lpw_a /= 2;
   I.c = g.c;
   I.K = g.K;
   I.alpha = g.alpha;
