@@ -318,7 +318,7 @@ KERNEL_OF_STAGE = {
 }
 
 
-def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision):
+def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision, out_path=None):
     """HBM bytes per launch of each stage from two rocprofv3 --pmc runs of
     `bench.py --calibrate-copy copy_bytes` (FETCH_SIZE, then WRITE_SIZE; both
     in KiB per dispatch).  Each counter is scaled by what it reads for the
@@ -376,10 +376,11 @@ def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision)
             out["raw_kib_per_launch"][key] = {"fetch": f_avg, "write": w_avg, "dispatches": len(ds),
                                               "grid_threads": grid, "kernel": name}
             out["bytes_per_launch"][key] = 1024.0 * (f_avg * f_scale + w_avg * w_scale)
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = out_path or os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     print(json.dumps(out, indent=1, sort_keys=True))
+    return out
 
 
 def main():
