@@ -1303,9 +1303,12 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
   PAT_END_ITEM
 }
 
-// k_tr_x1_r2c as a software pipeline (see k_tr_x2_pipe), for one instance
-// without a cut-off on this pass, len a multiple of 4, tb even and
-// n1 * tb / 2 <= kPipeU * kBlock four-sample loads per tile.
+// k_tr_x1_r2c as a software pipeline (see k_tr_x2_pipe), for one instance,
+// len a multiple of 4, tb even and n1 * tb / 2 <= kPipeU * kBlock
+// four-sample loads per tile.  With a cut-off on this (data-side) pass, two
+// LDS slices of the weight table alternate: the slice of the next tile's
+// column is written while the current tile is transformed, and read when
+// the next tile is stored into LDS.
 template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a);
 
@@ -1385,6 +1388,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a) {
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
   cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
+  const bool cut = !a.len_nz && I.cut_e;  // data-side pass with a cut-off
+  const int ew = (I.cut_e + 1) * (I.cut_e + 1);
+  T* cws0 = reinterpret_cast<T*>(buf + L * I.tb);  // two column slices of the weights
   load_twiddles(tw, I, I.f1);
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
@@ -1412,20 +1418,66 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a) {
     }
   };
   int item = blockIdx.x;
-  if (item < a.total) fetch(item);
-  for (; item < a.total; item += gridDim.x) {
+  if (item < a.total) {
+    fetch(item);
+    if (cut) {
+      cut_slice(I, cws0, item / ntile);
+      __syncthreads();
+    }
+  }
+  for (int it = 0; item < a.total; item += gridDim.x, ++it) {
+    const int x2 = item / ntile;
+    const int t0 = (item - x2 * ntile) * 2 * tb;
+    const T* cws = cws0 + (it & 1) * ew;
+    const int cb2 = cut && I.n2 > 1 ? cut_band(x2, I.n2, I.cut_e) : I.cut_e;
 #pragma unroll
     for (int u = 0; u < kPipeU; ++u) {
       const int e = (int)threadIdx.x + u * kBlock;
       if (e < L * hb) {
-        buf[2 * e] = pre[2 * u];
-        buf[2 * e + 1] = pre[2 * u + 1];
+        cx<T> v0 = pre[2 * u], v1 = pre[2 * u + 1];
+        if (cut) {
+          int x, c;
+          divmod<true>(e, hb, &x, &c);
+          if (t0 + 4 * c < len) {
+            cut_pair(I, cws, cb2, x, t0 + 4 * c, len, &v0);
+            cut_pair(I, cws, cb2, x, t0 + 4 * c + 2, len, &v1);
+          }
+        }
+        buf[2 * e] = v0;
+        buf[2 * e + 1] = v1;
       }
     }
     __syncthreads();
-    const int x2 = item / ntile;
-    const int t0 = (item - x2 * ntile) * 2 * tb;
-    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    if (item + (int)gridDim.x < a.total) {
+      // The next column's weights are loaded before the next tile and
+      // written to the other slice after it (last read before the barrier
+      // above): their LDS writes then wait for these loads only, not for
+      // the tile's.
+      const int nx2 = (item + (int)gridDim.x) / ntile;
+      T sv[2];
+      if (cut) {
+        const int e1 = I.cut_e + 1;
+        const int b2 = I.n2 > 1 ? cut_band(nx2, I.n2, I.cut_e) : I.cut_e;
+        const T* W = static_cast<const T*>(I.cutw);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = (int)threadIdx.x + h * kBlock;
+          if (e < ew) {
+            const int b1 = e / e1, b3 = e - b1 * e1;
+            sv[h] = W[(b1 * e1 + b2) * e1 + b3];
+          }
+        }
+      }
+      fetch(item + gridDim.x);
+      if (cut) {
+        T* dst = cws0 + ((it + 1) & 1) * ew;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = (int)threadIdx.x + h * kBlock;
+          if (e < ew) dst[e] = sv[h];
+        }
+      }
+    }
     fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
     cx<T>* out0 = out + (size_t)x2 * len + t0;
     for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
@@ -2309,9 +2361,11 @@ struct Runner {
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
     const int len = nz ? h[0].nz : h[0].nt;
-    if (sizeof(T) == 4 && n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
+    if (sizeof(T) == 4 && n == 1 && !a.counter && len % 4 == 0 && h[0].tb % 2 == 0 &&
         h[0].n1 * (h[0].tb / 2) <= kPipeU * kBlock) {
-      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
+      const size_t ew = (size_t)(h[0].cut_e + 1) * (h[0].cut_e + 1);
+      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t) +
+                         (!nz && h[0].cut_e ? 2 * ew * sizeof(T) : 0);
       return launch_persistent(k_tr_x1_pipe<T, RS>, "dft_x1", a, shm, st, tm);
     }
     return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
