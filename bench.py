@@ -310,8 +310,8 @@ def cpu_baseline(p_np, g, f_gpu, budget_s, np):
 
 KERNEL_OF_STAGE = {
     # library stage name -> kernel symbol prefixes in the profiler's output
-    "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<"),
-    "nufft_adjoint_fused": ("void pat::k_line_nufft1<",),
+    "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<", "void pat::k_line_nufft2_pipe_c<"),
+    "nufft_adjoint_fused": ("void pat::k_line_nufft1<", "void pat::k_line_nufft1_c<"),
     "dft_x1": ("void pat::k_tr_x1_r2c<", "void pat::k_tr_x1_pipe<"),
     "dft_x2": ("void pat::k_tr_x2<", "void pat::k_tr_x2_pipe<"),
     "idft_x1_c2r": ("void pat::k_tr_c2r_k1<", "void pat::k_tr_c2r_pipe<"),

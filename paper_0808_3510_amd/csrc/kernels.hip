@@ -18,8 +18,10 @@
 //   k_line_spread its transpose (type-1), gathered per grid cell over the
 //                 monotone node list of the line: no atomics, deterministic
 //   k_line_nufft2 a2 + a3 + inverse depth DFT fused per line group in LDS
-//                 (k_line_nufft2_pipe: its software pipeline for c = 2)
+//                 (k_line_nufft2_pipe: its software pipeline for c = 2;
+//                 k_line_nufft2_pipe_c: the same for sizes fixed at compile time)
 //   k_line_nufft1 depth DFT + spreading + transposed a2 fused per line in LDS
+//                 (k_line_nufft1_c: sizes fixed at compile time)
 // The fused kernels never store the oversampled grid; the staged ones do
 // (bf16 grid option, and the stand-alone a3 / spreading entry points).
 //
@@ -491,6 +493,47 @@ __device__ void fft_lds_p2_src_sink(cx<T>* buf, const FftDesc& d, const cx<T>* _
   else if (R == 4) fft_last_stage_p2<T, 4, BF>(buf, L, nb, bs, es, sink);
   else fft_last_stage_p2<T, 2, BF>(buf, L, nb, bs, es, sink);
   __syncthreads();
+}
+
+// Radix plan of 2^E points known at compile time, by the host plan's rule:
+// radix 8 while it divides, ending in 4 (E mod 3 = 2), 4 and 4 (E mod 3 = 1,
+// E >= 4), or 2 (E = 1).  With every length and stage a constant, the stage
+// loops, index shifts and output positions fold at compile time.
+template <int E>
+struct P2Plan {
+  static constexpr int n8 = E / 3, rem = E % 3;
+  static constexpr int nst = rem == 0 ? n8 : n8 + 1;
+  static constexpr int rad(int s) {
+    return rem == 0 ? 8 : rem == 2 ? (s < n8 ? 8 : 4) : n8 > 0 ? (s < n8 - 1 ? 8 : 4) : 2;
+  }
+  static constexpr int lbits(int s) { return rad(s) == 8 ? 3 : rad(s) == 4 ? 2 : 1; }
+  // log2 of the span Li that stage s works on
+  static constexpr int lspan(int s) { return s == 0 ? E : lspan(s - 1) - lbits(s - 1); }
+  // natural index of the output at position pos (digit reversal of the plan)
+  static __device__ __forceinline__ int natural(int pos) {
+    int k = 0, sh = 0;
+#pragma unroll
+    for (int s = 0; s < nst; ++s) {
+      const int lo = lspan(s) - lbits(s);
+      k += ((pos >> lo) & ((1 << lbits(s)) - 1)) << sh;
+      sh += lbits(s);
+    }
+    return k;
+  }
+};
+static_assert(P2Plan<10>::nst == 4 && P2Plan<10>::rad(0) == 8 && P2Plan<10>::rad(2) == 4, "plan of 1024");
+static_assert(P2Plan<8>::nst == 3 && P2Plan<8>::rad(2) == 4 && P2Plan<9>::rad(2) == 8, "plans of 256, 512");
+
+// Stages S .. nst - 2 (twiddled, in place) of the compile-time plan of 2^E
+// points on nb lines of stride 2^E, one block barrier after each.
+template <typename T, int E, int S>
+__device__ __forceinline__ void p2_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int nb) {
+  using Pl = P2Plan<E>;
+  if constexpr (S + 1 < Pl::nst) {
+    fft_stage<T, Pl::rad(S), true, true>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
+    __syncthreads();
+    p2_stages<T, E, S + 1>(buf, tw, nb);
+  }
 }
 
 // fft_lds for power-of-two lengths whose result goes to sink(b, blk, v[R])
@@ -2131,6 +2174,91 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft2_pipe(StageArgs a) {
   }
 }
 
+// k_line_nufft2_pipe for m = 2^LM and nz = 2^LZ known at compile time (the
+// line group then holds 2^(11 - LM) lines): the same work, with the FFT
+// stages, their loops and the output positions fixed by P2Plan.  Four waves
+// per SIMD: at the five-wave register cap (96) the unrolled stages spill.
+template <typename T, int TAPS, int LM, int LZ>
+__global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
+  const Inst& I = *a.inst[0];
+  constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, lpw = 2048 / m;
+  using PM = P2Plan<LM>;
+  using PZ = P2Plan<LZ>;
+  static_assert(PM::rad(0) == 8 && PM::nst >= 2 && LZ <= LM, "pipelined first stage");
+  const int sub = m >> 3, lsub = __builtin_ctz((unsigned)sub);
+  const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT scratch, later the depth lines
+  cx<T>* gn = gp + lpw * m;                          // grid lines in natural order
+  const T* sn = static_cast<const T*>(I.sn);
+  const int q = nt >> 2;
+  // inputs r = 0, 1, 6, 7 of the butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
+  const int ns[4] = {j + 2 * q, j + 3 * q, j, j + q};
+  T snr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) snr[i] = sn[ns[i]];
+  const cx<T> w1 = twm[j];
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
+  cx<T>* outb = static_cast<cx<T>*>(a.out[0]);
+  cx<T> pre[4];
+  auto fetch = [&](int item) {
+    const int line0 = item * lpw;
+    const bool ok = line0 + bb < I.lines;
+    const cx<T>* gin = in + (size_t)(line0 + bb) * nt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pre[i] = ok ? gin[ns[i]] : mk(T(0), T(0));
+  };
+  constexpr int step = m / PM::rad(PM::nst - 1);
+  constexpr int stepz = nz / PZ::rad(PZ::nst - 1);
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+    const int line0 = item * lpw;
+    const int nl = min(lpw, I.lines - line0);
+    {
+      cx<T> v[8];
+      v[0] = cscl(pre[0], snr[0]);
+      v[1] = cscl(pre[1], snr[1]);
+      v[2] = v[3] = v[4] = v[5] = mk(T(0), T(0));
+      v[6] = cscl(pre[2], snr[2]);
+      v[7] = cscl(pre[3], snr[3]);
+      dft_pow2<T, 8>(v);
+      twiddle_pow2<T, 8>(v, w1);
+      cx<T>* p = gp + bb * m + j;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) p[r * sub] = v[r];
+    }
+    __syncthreads();
+    p2_stages<T, LM, 1>(gp, twm, lpw);
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    auto sink = [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* g = gn + b * m;
+      const int k0 = PM::natural(blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) g[k0 + r * step] = v[r];
+    };
+    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true>(gp, m, lpw, m, 1, sink);
+    __syncthreads();
+    cx<T>* fz = gp;
+    interp_lines<T, TAPS, true, true, false>(I, a, gn, m, [&](int b) { return line_ak(I, line0 + b); }, nl, a.mode,
+                                             [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    __syncthreads();
+    cx<T>* out = outb + (size_t)line0 * nz;
+    p2_stages<T, LZ, 0>(fz, twz, lpw);
+    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(fz, nz, lpw, nz, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      if (b >= nl) return;
+      cx<T>* o = out + b * nz;
+      const int k0 = PZ::natural(blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[k0 + r * stepz] = cconj(v[r]);
+    });
+    __syncthreads();
+  }
+}
+
 // Fused depth DFT + spreading + transposed a2 (operators R^T and A).  A work
 // item holds lpw_a lines: their depth DFTs run together (power-of-two
 // builds: the first stage reads the spectra from memory and the last writes
@@ -2191,6 +2319,75 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
     }
     __syncthreads();
     ifft_pick_deconv<T, RS>(I, grid, 1, static_cast<cx<T>*>(a.out[inst_]) + (size_t)(line0 + b) * nt, twm);
+  }
+  PAT_END_ITEM
+}
+
+// k_line_nufft1 for m = 2^LM and nz = 2^LZ known at compile time (FP32,
+// one instance): the same work, with both FFTs' stages fixed by P2Plan; the
+// last stage of the grid FFT writes the picked, deconvolved samples straight
+// to memory.  Five waves per SIMD (the register cap of 96 costs a 20-byte
+// spill): the spreading is bound by instruction issue and gains more from
+// the fifth wave than the spill takes.
+template <typename T, int TAPS, int LM, int LZ>
+__global__ __launch_bounds__(kBlock, 5) void k_line_nufft1_c(StageArgs a) {
+  constexpr int m = 1 << LM, nz = 1 << LZ;
+  using PM = P2Plan<LM>;
+  using PZ = P2Plan<LZ>;
+  static_assert(PM::nst >= 2 && PZ::nst >= 2, "two or more stages");
+  PAT_FOR_EACH_ITEM(a)
+  const int nt = I.nt;
+  const int lpw = I.lpw_a;
+  const int line0 = li * lpw;
+  const int nl = min(lpw, I.lines - line0);
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  const int sg = m > lpw * nz ? m : lpw * nz;
+  cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // depth-FFT scratch, then one grid line
+  cx<T>* qn = grid + sg;                              // lpw depth spectra, natural order
+  const SpreadLds<T, 2> L = SpreadLds<T, 2>::carve(qn + lpw * nz, nz, I.taps);
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nz;
+  constexpr int stepz = nz / PZ::rad(PZ::nst - 1);
+  fft_first_stage_p2<T, PZ::rad(0), true>(grid, nz, twz, nl, nz, 1,
+                                          [&](int b, int pos) { return in[(size_t)b * nz + pos]; });
+  __syncthreads();
+  p2_stages<T, LZ, 1>(grid, twz, nl);
+  fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(grid, nz, nl, nz, 1, [&](int b, int blk, const auto& v) {
+    constexpr int R = sizeof(v) / sizeof(v[0]);
+    cx<T>* d = qn + b * nz;
+    const int k0 = PZ::natural(blk * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[k0 + r * stepz] = v[r];
+  });
+  __syncthreads();
+  auto put = [&](int j, cx<T> v) { grid[j] = cconj(v); };
+  auto put4 = [&](int j, const cx<T>* v) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) grid[j + c] = cconj(v[c]);
+  };
+  const T* sn = static_cast<const T*>(I.sn);
+  constexpr int step = m / PM::rad(PM::nst - 1);
+  for (int b = 0; b < nl; ++b) {
+    const cx<T>* qb = qn + b * nz;
+    auto fget = [&](int l) { return qb[l]; };
+    if (TAPS > 0 && a.pair_ok) {
+      spread_line<T, (TAPS > 0 ? TAPS : 2), true>(I, a, line0 + b, a.mode, L, fget, put, put4);
+    } else {
+      spread_line<T, 0, false>(I, a, line0 + b, a.mode, L, fget, put, put4);
+    }
+    __syncthreads();
+    // X_n = s_n conj(G_k) for the natural index k = (n - nt/2) mod m
+    cx<T>* x = static_cast<cx<T>*>(a.out[inst_]) + (size_t)(line0 + b) * nt;
+    p2_stages<T, LM, 0>(grid, twm, 1);
+    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true>(grid, m, 1, m, 1, [&](int, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      const int k0 = PM::natural(blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n = (k0 + r * step + nt / 2) & (m - 1);
+        if (n < nt) x[n] = cscl(cconj(v[r]), sn[n]);
+      }
+    });
   }
   PAT_END_ITEM
 }
@@ -2436,14 +2633,48 @@ struct Runner {
     if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
       const Inst& I = h[0];
       if (n == 1 && !a.counter && a.pair_ok && I.m == 2 * I.nt && I.m >= I.nz && I.fm.nst >= 2 &&
-          I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock)
-        return launch_persistent(k_line_nufft2_pipe<T, TAPS>, "nufft_fused", a, lds_fused2(I, cs), st, tm);
+          I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock) {
+        // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2
+        const size_t shm = lds_fused2(I, cs);
+        const int lm = __builtin_ctz((unsigned)I.m), dz = lm - __builtin_ctz((unsigned)I.nz);
+        auto go = [&](auto kern) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm); };
+        if (dz == 2) {
+          if (lm == 8) return go(k_line_nufft2_pipe_c<T, TAPS, 8, 6>);
+          if (lm == 9) return go(k_line_nufft2_pipe_c<T, TAPS, 9, 7>);
+          if (lm == 10) return go(k_line_nufft2_pipe_c<T, TAPS, 10, 8>);
+          if (lm == 11) return go(k_line_nufft2_pipe_c<T, TAPS, 11, 9>);
+        } else if (dz == 1) {
+          if (lm == 8) return go(k_line_nufft2_pipe_c<T, TAPS, 8, 7>);
+          if (lm == 9) return go(k_line_nufft2_pipe_c<T, TAPS, 9, 8>);
+          if (lm == 10) return go(k_line_nufft2_pipe_c<T, TAPS, 10, 9>);
+          if (lm == 11) return go(k_line_nufft2_pipe_c<T, TAPS, 11, 10>);
+        }
+        return go(k_line_nufft2_pipe<T, TAPS>);
+      }
     }
     return launch(k_line_nufft2<T, RS, TAPS>, "nufft_fused", a,
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LA, true, mode, in, out);
+    if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
+      // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2
+      const Inst& I = h[0];
+      const int lm = __builtin_ctz((unsigned)I.m), dz = lm - __builtin_ctz((unsigned)I.nz);
+      const size_t shm = lds_fused1(I, cs);
+      auto go = [&](auto kern) { return launch(kern, "nufft_adjoint_fused", a, shm, st, tm); };
+      if (n == 1 && dz == 2) {
+        if (lm == 8) return go(k_line_nufft1_c<T, TAPS, 8, 6>);
+        if (lm == 9) return go(k_line_nufft1_c<T, TAPS, 9, 7>);
+        if (lm == 10) return go(k_line_nufft1_c<T, TAPS, 10, 8>);
+        if (lm == 11) return go(k_line_nufft1_c<T, TAPS, 11, 9>);
+      } else if (n == 1 && dz == 1) {
+        if (lm == 8) return go(k_line_nufft1_c<T, TAPS, 8, 7>);
+        if (lm == 9) return go(k_line_nufft1_c<T, TAPS, 9, 8>);
+        if (lm == 10) return go(k_line_nufft1_c<T, TAPS, 10, 9>);
+        if (lm == 11) return go(k_line_nufft1_c<T, TAPS, 11, 10>);
+      }
+    }
     return launch(k_line_nufft1<T, RS, TAPS>, "nufft_adjoint_fused", a,
                   max_over([](const Inst& I) { return lds_fused1(I, cs); }), st, tm);
   }

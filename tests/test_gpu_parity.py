@@ -166,6 +166,11 @@ def test_spread_lines_is_adjoint_of_interp_lines(prec):
     geo(64, 64, 128, 64, 1.0, 0.9, 1.1),           # fused pipeline, three-stage FFTs
     geo(32, 1, 64, 32),                            # 2D: 17 lines, a short last group
     geo(24, 20, 48, 24, 1.0, 0.8, 1.2),            # transverse pipelines, general radices
+    # fused pipeline with compile-time sizes: (m, nz) = (256, 128), (512, 256), (2048, 512)
+    geo(16, 16, 128, 128, 1.0, 0.9, 1.1),
+    geo(12, 1, 256, 256),
+    geo(8, 1, 1024, 512, 1.0, 1.1, 0.9),
+    geo(8, 1, 1024, 256),                          # nz = m/8: the fused pipeline with run-time sizes
 ])
 def test_pipelined_kernels_match_one_tile_kernels(g):
     """A single FP32 plan runs the software-pipelined persistent kernels; the
@@ -181,3 +186,37 @@ def test_pipelined_kernels_match_one_tile_kernels(g):
     b = outs[0]
     assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() < 1e-6
     assert relerr(a.cpu().double().numpy(), recon.reconstruct(p, g)) < TOL["f32"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_spreading_repeats_bit_for_bit(prec):
+    """Spreading gathers each cell's nodes in node order, with no atomics:
+    repeated runs of R^T and A agree bit for bit (128^3 volume, whose lines
+    of large |K| crowd many nodes into a few cells)."""
+    g = geo(128, 128, 256, 128, 1 / 128, 1 / 128, 1 / 128)
+    say(f"repeatability {prec} {g}")
+    plan = make_plan(g, prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    q = torch.randn((128, 128, 128), device=DEV, dtype=dt, generator=gen)
+    for op in ("reconstruct_adjoint", "forward"):
+        first = getattr(plan, op)(q).clone()
+        for _ in range(3):
+            assert torch.equal(getattr(plan, op)(q), first)
+
+
+@pytest.mark.parametrize("op", ["reconstruct_adjoint", "forward"])
+@pytest.mark.parametrize("g", [
+    geo(64, 64, 128, 64, 1.0, 0.9, 1.1),           # compile-time sizes (m, nz) = (256, 64)
+    geo(16, 16, 128, 128, 1.0, 0.9, 1.1),          # (256, 128)
+    geo(12, 1, 256, 256),                          # (512, 256), 2D
+    geo(8, 1, 1024, 512, 1.0, 1.1, 0.9),           # (2048, 512), 2D
+    geo(8, 1, 1024, 256),                          # nz = m/8: run-time sizes
+])
+def test_fused_adjoint_sizes_match_oracle(op, g):
+    say(f"fused adjoint {op} {g}")
+    x = inputs.random_array((g["n1"], g["n2"], g["nz"]) if g["n2"] > 1 else (g["n1"], g["nz"]), 720)
+    plan = make_plan(g, "f32")
+    y = getattr(plan, op)(to_dev(x, "f32"))
+    torch.cuda.synchronize()
+    assert relerr(y.cpu().double().numpy(), getattr(recon, op)(x, g)) < TOL["f32"]
