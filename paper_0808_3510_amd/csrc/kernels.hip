@@ -536,6 +536,18 @@ __device__ __forceinline__ void p2_stages(cx<T>* buf, const cx<T>* __restrict__ 
   }
 }
 
+// Every stage (in place, each followed by a block barrier) of the
+// compile-time plan of 2^E points: fft_lds with the sizes fixed.
+template <typename T, int E, bool BF, int S = 0>
+__device__ __forceinline__ void p2_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int nb, int bs, int es) {
+  using Pl = P2Plan<E>;
+  if constexpr (S < Pl::nst) {
+    fft_stage<T, Pl::rad(S), true, BF>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, bs, es);
+    __syncthreads();
+    p2_fft<T, E, BF, S + 1>(buf, tw, nb, bs, es);
+  }
+}
+
 // fft_lds for power-of-two lengths whose result goes to sink(b, blk, v[R])
 // from the last stage (see fft_last_stage_p2) rather than back into buf.
 template <typename T, bool BF, typename Sink>
@@ -1351,9 +1363,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 // four-sample loads per tile.  With a cut-off on this (data-side) pass, two
 // LDS slices of the weight table alternate: the slice of the next tile's
 // column is written while the current tile is transformed, and read when
-// the next tile is stored into LDS.
-template <typename T, int RS>
-__global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a);
+// the next tile is stored into LDS.  LL > 0 fixes the transform length at
+// 2^LL (and its FFT stages) at compile time, in all three pipelines.
+template <typename T, int RS, int LL = 0>
+__global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a);
 
 // k_tr_x2 as a software pipeline for one instance whose tile is at most
 // kPipeU column pairs per thread (n2 * tb / 2 <= kPipeU * kBlock, tb even): a
@@ -1363,10 +1376,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a);
 // written back.  The output positions sit in LDS beside the twiddles (a
 // table read from memory in the store loop would wait for those loads).
 constexpr int kPipeU = 8;
-template <typename T, int RS>
+template <typename T, int RS, int LL = 0>
 __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
-  const int L = I.n2;
+  const int L = LL > 0 ? 1 << LL : I.n2;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
   cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
@@ -1410,7 +1423,8 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
     const int t0 = (item - k1 * ntile) * tb;
     cx<T>* io = base + (size_t)k1 * L * len + t0;
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
-    fft_lds<T, RS, false>(buf, I.f2, tw, tb, 1, tb);
+    if constexpr (LL > 0) p2_fft<T, (LL > 0 ? LL : 1), false>(buf, tw, tb, 1, tb);
+    else fft_lds<T, RS, false>(buf, I.f2, tw, tb, 1, tb);
     for (int e = threadIdx.x; e < L * hb; e += kBlock) {
       int kk, c;
       divmod<true>(e, hb, &kk, &c);
@@ -1423,11 +1437,11 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   }
 }
 
-template <typename T, int RS>
-__global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a) {
+template <typename T, int RS, int LL>
+__global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a) {
   constexpr bool P2 = RS == 0;
   const Inst& I = *a.inst[0];
-  const int L = I.n1;
+  const int L = LL > 0 ? 1 << LL : I.n1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
   cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
@@ -1521,7 +1535,8 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_pipe(StageArgs a) {
         }
       }
     }
-    fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
+    if constexpr (LL > 0) p2_fft<T, (LL > 0 ? LL : 1), false>(buf, tw, tb, 1, tb);
+    else fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
     cx<T>* out0 = out + (size_t)x2 * len + t0;
     for (int e = threadIdx.x; e < I.h1 * tb; e += kBlock) {
       int kk, b;
@@ -1624,10 +1639,10 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 // k_tr_c2r_k1 as a software pipeline (see k_tr_x2_pipe), for one instance
 // without a cut-off on this pass, len a multiple of 4, tb even and
 // n1 * tb <= 2 kPipeU * kBlock bins per tile.
-template <typename T, int RS>
-__global__ __launch_bounds__(kBlock) void k_tr_c2r_pipe(StageArgs a) {
+template <typename T, int RS, int LL = 0>
+__global__ __launch_bounds__(kBlock, 4) void k_tr_c2r_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
-  const int L = I.n1, half = L / 2;
+  const int L = LL > 0 ? 1 << LL : I.n1, half = L / 2;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   int32_t* pos = reinterpret_cast<int32_t*>(tw + L);
   cx<T>* buf = reinterpret_cast<cx<T>*>(pos + ((L + 3) & ~3));
@@ -1680,7 +1695,8 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_pipe(StageArgs a) {
     const int x2 = item / ntile;
     const int t0 = (item - x2 * ntile) * 2 * tb;
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
-    fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
+    if constexpr (LL > 0) p2_fft<T, (LL > 0 ? LL : 1), false>(buf, tw, tb, 1, tb);
+    else fft_lds<T, RS, false>(buf, I.f1, tw, tb, 1, tb);
     T* out0 = out + (size_t)x2 * len + t0;
     for (int e = threadIdx.x; e < L * hb; e += kBlock) {
       int x, c;
@@ -2563,6 +2579,12 @@ struct Runner {
       const size_t ew = (size_t)(h[0].cut_e + 1) * (h[0].cut_e + 1);
       const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t) +
                          (!nz && h[0].cut_e ? 2 * ew * sizeof(T) : 0);
+      if constexpr (RS == 0) {  // transform lengths 128, 256, 512 fixed at compile time
+        const int L = h[0].n1;
+        if (L == 128) return launch_persistent(k_tr_x1_pipe<T, RS, 7>, "dft_x1", a, shm, st, tm);
+        if (L == 256) return launch_persistent(k_tr_x1_pipe<T, RS, 8>, "dft_x1", a, shm, st, tm);
+        if (L == 512) return launch_persistent(k_tr_x1_pipe<T, RS, 9>, "dft_x1", a, shm, st, tm);
+      }
       return launch_persistent(k_tr_x1_pipe<T, RS>, "dft_x1", a, shm, st, tm);
     }
     return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
@@ -2573,7 +2595,14 @@ struct Runner {
     // (float only: the double registers of a prefetched tile halve occupancy)
     if (sizeof(T) == 4 && n == 1 && !a.counter && h[0].tb % 2 == 0 && h[0].n2 * (h[0].tb / 2) <= kPipeU * kBlock) {
       const size_t shm = lds_tile_x2(h[0], cs) + (size_t)((h[0].n2 + 3) & ~3) * sizeof(int32_t);
-      return launch_persistent(k_tr_x2_pipe<T, RS>, inv ? "idft_x2" : "dft_x2", a, shm, st, tm);
+      const char* name = inv ? "idft_x2" : "dft_x2";
+      if constexpr (RS == 0) {
+        const int L = h[0].n2;
+        if (L == 128) return launch_persistent(k_tr_x2_pipe<T, RS, 7>, name, a, shm, st, tm);
+        if (L == 256) return launch_persistent(k_tr_x2_pipe<T, RS, 8>, name, a, shm, st, tm);
+        if (L == 512) return launch_persistent(k_tr_x2_pipe<T, RS, 9>, name, a, shm, st, tm);
+      }
+      return launch_persistent(k_tr_x2_pipe<T, RS>, name, a, shm, st, tm);
     }
     return launch(k_tr_x2<T, RS>, inv ? "idft_x2" : "dft_x2", a,
                   max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
@@ -2584,6 +2613,12 @@ struct Runner {
     if (sizeof(T) == 4 && n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
         h[0].n1 * h[0].tb <= 2 * kPipeU * kBlock) {
       const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
+      if constexpr (RS == 0) {
+        const int L = h[0].n1;
+        if (L == 128) return launch_persistent(k_tr_c2r_pipe<T, RS, 7>, "idft_x1_c2r", a, shm, st, tm);
+        if (L == 256) return launch_persistent(k_tr_c2r_pipe<T, RS, 8>, "idft_x1_c2r", a, shm, st, tm);
+        if (L == 512) return launch_persistent(k_tr_c2r_pipe<T, RS, 9>, "idft_x1_c2r", a, shm, st, tm);
+      }
       return launch_persistent(k_tr_c2r_pipe<T, RS>, "idft_x1_c2r", a, shm, st, tm);
     }
     return launch(k_tr_c2r_k1<T, RS>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),

@@ -171,6 +171,11 @@ def test_spread_lines_is_adjoint_of_interp_lines(prec):
     geo(12, 1, 256, 256),
     geo(8, 1, 1024, 512, 1.0, 1.1, 0.9),
     geo(8, 1, 1024, 256),                          # nz = m/8: the fused pipeline with run-time sizes
+    # transverse pipelines with compile-time lengths 128 and 512 on each axis
+    geo(128, 8, 16, 8, 1.0, 0.9, 1.1),
+    geo(8, 128, 16, 8, 1.0, 0.9, 1.1),
+    geo(512, 1, 16, 8),
+    geo(4, 512, 8, 8),
 ])
 def test_pipelined_kernels_match_one_tile_kernels(g):
     """A single FP32 plan runs the software-pipelined persistent kernels; the
