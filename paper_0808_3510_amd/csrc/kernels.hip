@@ -1376,6 +1376,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a);
 // written back.  The output positions sit in LDS beside the twiddles (a
 // table read from memory in the store loop would wait for those loads).
 constexpr int kPipeU = 8;
+// tile width of the FP32 plans (16 columns, 8 once a tile of 2^9-point
+// columns would pass 64 KB of LDS), fixed with the length in the instances
+// that take it at compile time
+constexpr int pipe_tb(int ll) { return ll >= 9 ? 8 : 16; }
 template <typename T, int RS, int LL = 0>
 __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
@@ -1387,7 +1391,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   const int32_t* perm = I.perm + I.f2.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + tb - 1) / tb;
   const bool inv = a.mode != 0;
   cx<T>* base = static_cast<cx<T>*>(a.out[0]);
@@ -1452,7 +1456,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a) {
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const size_t rstride = (size_t)I.n2 * len;
   const T* in = static_cast<const T*>(a.in[0]);
@@ -1650,7 +1654,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tr_c2r_pipe(StageArgs a) {
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const size_t rstride = (size_t)I.n2 * len;
   const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
@@ -2581,9 +2585,12 @@ struct Runner {
                          (!nz && h[0].cut_e ? 2 * ew * sizeof(T) : 0);
       if constexpr (RS == 0) {  // transform lengths 128, 256, 512 fixed at compile time
         const int L = h[0].n1;
-        if (L == 128) return launch_persistent(k_tr_x1_pipe<T, RS, 7>, "dft_x1", a, shm, st, tm);
-        if (L == 256) return launch_persistent(k_tr_x1_pipe<T, RS, 8>, "dft_x1", a, shm, st, tm);
-        if (L == 512) return launch_persistent(k_tr_x1_pipe<T, RS, 9>, "dft_x1", a, shm, st, tm);
+        if (L == 128 && h[0].tb == pipe_tb(7))
+          return launch_persistent(k_tr_x1_pipe<T, RS, 7>, "dft_x1", a, shm, st, tm);
+        if (L == 256 && h[0].tb == pipe_tb(8))
+          return launch_persistent(k_tr_x1_pipe<T, RS, 8>, "dft_x1", a, shm, st, tm);
+        if (L == 512 && h[0].tb == pipe_tb(9))
+          return launch_persistent(k_tr_x1_pipe<T, RS, 9>, "dft_x1", a, shm, st, tm);
       }
       return launch_persistent(k_tr_x1_pipe<T, RS>, "dft_x1", a, shm, st, tm);
     }
@@ -2598,9 +2605,9 @@ struct Runner {
       const char* name = inv ? "idft_x2" : "dft_x2";
       if constexpr (RS == 0) {
         const int L = h[0].n2;
-        if (L == 128) return launch_persistent(k_tr_x2_pipe<T, RS, 7>, name, a, shm, st, tm);
-        if (L == 256) return launch_persistent(k_tr_x2_pipe<T, RS, 8>, name, a, shm, st, tm);
-        if (L == 512) return launch_persistent(k_tr_x2_pipe<T, RS, 9>, name, a, shm, st, tm);
+        if (L == 128 && h[0].tb == pipe_tb(7)) return launch_persistent(k_tr_x2_pipe<T, RS, 7>, name, a, shm, st, tm);
+        if (L == 256 && h[0].tb == pipe_tb(8)) return launch_persistent(k_tr_x2_pipe<T, RS, 8>, name, a, shm, st, tm);
+        if (L == 512 && h[0].tb == pipe_tb(9)) return launch_persistent(k_tr_x2_pipe<T, RS, 9>, name, a, shm, st, tm);
       }
       return launch_persistent(k_tr_x2_pipe<T, RS>, name, a, shm, st, tm);
     }
@@ -2615,9 +2622,12 @@ struct Runner {
       const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
       if constexpr (RS == 0) {
         const int L = h[0].n1;
-        if (L == 128) return launch_persistent(k_tr_c2r_pipe<T, RS, 7>, "idft_x1_c2r", a, shm, st, tm);
-        if (L == 256) return launch_persistent(k_tr_c2r_pipe<T, RS, 8>, "idft_x1_c2r", a, shm, st, tm);
-        if (L == 512) return launch_persistent(k_tr_c2r_pipe<T, RS, 9>, "idft_x1_c2r", a, shm, st, tm);
+        if (L == 128 && h[0].tb == pipe_tb(7))
+          return launch_persistent(k_tr_c2r_pipe<T, RS, 7>, "idft_x1_c2r", a, shm, st, tm);
+        if (L == 256 && h[0].tb == pipe_tb(8))
+          return launch_persistent(k_tr_c2r_pipe<T, RS, 8>, "idft_x1_c2r", a, shm, st, tm);
+        if (L == 512 && h[0].tb == pipe_tb(9))
+          return launch_persistent(k_tr_c2r_pipe<T, RS, 9>, "idft_x1_c2r", a, shm, st, tm);
       }
       return launch_persistent(k_tr_c2r_pipe<T, RS>, "idft_x1_c2r", a, shm, st, tm);
     }
