@@ -1366,7 +1366,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 // the next tile is stored into LDS.  LL > 0 fixes the transform length at
 // 2^LL (and its FFT stages) at compile time, in all three pipelines.
 template <typename T, int RS, int LL = 0>
-__global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a);
+__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArgs a);
 
 // k_tr_x2 as a software pipeline for one instance whose tile is at most
 // kPipeU column pairs per thread (n2 * tb / 2 <= kPipeU * kBlock, tb even): a
@@ -1442,7 +1442,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
 }
 
 template <typename T, int RS, int LL>
-__global__ __launch_bounds__(kBlock, 4) void k_tr_x1_pipe(StageArgs a) {
+__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArgs a) {
   constexpr bool P2 = RS == 0;
   const Inst& I = *a.inst[0];
   const int L = LL > 0 ? 1 << LL : I.n1;
@@ -1644,7 +1644,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 // without a cut-off on this pass, len a multiple of 4, tb even and
 // n1 * tb <= 2 kPipeU * kBlock bins per tile.
 template <typename T, int RS, int LL = 0>
-__global__ __launch_bounds__(kBlock, 4) void k_tr_c2r_pipe(StageArgs a) {
+__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_c2r_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
   const int L = LL > 0 ? 1 << LL : I.n1, half = L / 2;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
@@ -2575,61 +2575,64 @@ struct Runner {
     return mx;
   }
 
+  // The pipelined transverse kernels run for one FP32 instance (double
+  // registers of a prefetched tile would halve occupancy); lengths of 128, 256
+  // and 512 points with the plan's tile width take the compile-time instances.
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
     const int len = nz ? h[0].nz : h[0].nt;
-    if (sizeof(T) == 4 && n == 1 && !a.counter && len % 4 == 0 && h[0].tb % 2 == 0 &&
-        h[0].n1 * (h[0].tb / 2) <= kPipeU * kBlock) {
-      const size_t ew = (size_t)(h[0].cut_e + 1) * (h[0].cut_e + 1);
-      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t) +
-                         (!nz && h[0].cut_e ? 2 * ew * sizeof(T) : 0);
-      if constexpr (RS == 0) {  // transform lengths 128, 256, 512 fixed at compile time
-        const int L = h[0].n1;
-        if (L == 128 && h[0].tb == pipe_tb(7))
-          return launch_persistent(k_tr_x1_pipe<T, RS, 7>, "dft_x1", a, shm, st, tm);
-        if (L == 256 && h[0].tb == pipe_tb(8))
-          return launch_persistent(k_tr_x1_pipe<T, RS, 8>, "dft_x1", a, shm, st, tm);
-        if (L == 512 && h[0].tb == pipe_tb(9))
-          return launch_persistent(k_tr_x1_pipe<T, RS, 9>, "dft_x1", a, shm, st, tm);
+    if constexpr (sizeof(T) == 4) {
+      if (n == 1 && !a.counter && len % 4 == 0 && h[0].tb % 2 == 0 && h[0].n1 * (h[0].tb / 2) <= kPipeU * kBlock) {
+        const size_t ew = (size_t)(h[0].cut_e + 1) * (h[0].cut_e + 1);
+        const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t) +
+                           (!nz && h[0].cut_e ? 2 * ew * sizeof(T) : 0);
+        auto go = [&](auto kern) { return launch_persistent(kern, "dft_x1", a, shm, st, tm); };
+        if constexpr (RS == 0) {
+          const int L = h[0].n1, tb = h[0].tb;
+          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_x1_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_x1_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_x1_pipe<T, RS, 9>);
+        }
+        return go(k_tr_x1_pipe<T, RS>);
       }
-      return launch_persistent(k_tr_x1_pipe<T, RS>, "dft_x1", a, shm, st, tm);
     }
     return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
                   tm);
   }
   hipError_t x2(void* const* io, bool nz, int inv) {
     StageArgs a = base(IT_X2, nz, inv, io, io);
-    // (float only: the double registers of a prefetched tile halve occupancy)
-    if (sizeof(T) == 4 && n == 1 && !a.counter && h[0].tb % 2 == 0 && h[0].n2 * (h[0].tb / 2) <= kPipeU * kBlock) {
-      const size_t shm = lds_tile_x2(h[0], cs) + (size_t)((h[0].n2 + 3) & ~3) * sizeof(int32_t);
-      const char* name = inv ? "idft_x2" : "dft_x2";
-      if constexpr (RS == 0) {
-        const int L = h[0].n2;
-        if (L == 128 && h[0].tb == pipe_tb(7)) return launch_persistent(k_tr_x2_pipe<T, RS, 7>, name, a, shm, st, tm);
-        if (L == 256 && h[0].tb == pipe_tb(8)) return launch_persistent(k_tr_x2_pipe<T, RS, 8>, name, a, shm, st, tm);
-        if (L == 512 && h[0].tb == pipe_tb(9)) return launch_persistent(k_tr_x2_pipe<T, RS, 9>, name, a, shm, st, tm);
+    const char* name = inv ? "idft_x2" : "dft_x2";
+    if constexpr (sizeof(T) == 4) {
+      if (n == 1 && !a.counter && h[0].tb % 2 == 0 && h[0].n2 * (h[0].tb / 2) <= kPipeU * kBlock) {
+        const size_t shm = lds_tile_x2(h[0], cs) + (size_t)((h[0].n2 + 3) & ~3) * sizeof(int32_t);
+        auto go = [&](auto kern) { return launch_persistent(kern, name, a, shm, st, tm); };
+        if constexpr (RS == 0) {
+          const int L = h[0].n2, tb = h[0].tb;
+          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_x2_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_x2_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_x2_pipe<T, RS, 9>);
+        }
+        return go(k_tr_x2_pipe<T, RS>);
       }
-      return launch_persistent(k_tr_x2_pipe<T, RS>, name, a, shm, st, tm);
     }
-    return launch(k_tr_x2<T, RS>, inv ? "idft_x2" : "dft_x2", a,
-                  max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
+    return launch(k_tr_x2<T, RS>, name, a, max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
   }
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_C2R, nz, 0, in, out);
     const int len = nz ? h[0].nz : h[0].nt;
-    if (sizeof(T) == 4 && n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
-        h[0].n1 * h[0].tb <= 2 * kPipeU * kBlock) {
-      const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
-      if constexpr (RS == 0) {
-        const int L = h[0].n1;
-        if (L == 128 && h[0].tb == pipe_tb(7))
-          return launch_persistent(k_tr_c2r_pipe<T, RS, 7>, "idft_x1_c2r", a, shm, st, tm);
-        if (L == 256 && h[0].tb == pipe_tb(8))
-          return launch_persistent(k_tr_c2r_pipe<T, RS, 8>, "idft_x1_c2r", a, shm, st, tm);
-        if (L == 512 && h[0].tb == pipe_tb(9))
-          return launch_persistent(k_tr_c2r_pipe<T, RS, 9>, "idft_x1_c2r", a, shm, st, tm);
+    if constexpr (sizeof(T) == 4) {
+      if (n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
+          h[0].n1 * h[0].tb <= 2 * kPipeU * kBlock) {
+        const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
+        auto go = [&](auto kern) { return launch_persistent(kern, "idft_x1_c2r", a, shm, st, tm); };
+        if constexpr (RS == 0) {
+          const int L = h[0].n1, tb = h[0].tb;
+          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_c2r_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_c2r_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_c2r_pipe<T, RS, 9>);
+        }
+        return go(k_tr_c2r_pipe<T, RS>);
       }
-      return launch_persistent(k_tr_c2r_pipe<T, RS>, "idft_x1_c2r", a, shm, st, tm);
     }
     return launch(k_tr_c2r_k1<T, RS>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
                   st, tm);
