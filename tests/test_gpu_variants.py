@@ -50,10 +50,11 @@ def test_methods_run_the_reconstruction_only():
     assert ei.value.status == 2
 
 
-# Kaiser-Bessel over the oversampling factors of Fig. 5 (2cK taps capped at
-# 64, so K = 2 at c = 16).  The last geometry has an 8192-point grid line at
-# c = 16: its fused kernel holds 131 KB of LDS.
-KB_SWEEP = [(4.0, 3.0), (8.0, 3.0), (16.0, 2.0)]
+# Kaiser-Bessel over the oversampling factors of Fig. 5 and one step past
+# them (2cK taps capped at 64, so K = 2 at c = 16 and K = 1 at c = 32).  The
+# last geometry has an 8192-point grid line at c = 16: its fused kernel holds
+# 131 KB of LDS; at c = 32 its 16384-point line does not fit one workgroup.
+KB_SWEEP = [(4.0, 3.0), (8.0, 3.0), (16.0, 2.0), (32.0, 1.0)]
 KB_GEOS = GEOS[:2] + [dict(n1=16, n2=1, nt=512, nz=64, dx=1 / 16, dt=1 / 512, dz=1 / 64, vs=1.0)]
 
 
@@ -65,6 +66,8 @@ def test_kaiser_bessel_oversampling_sweep(fused, prec, c, K, gi):
     g = KB_GEOS[gi]
     if prec == "f64" and c * g["nt"] * 16 > 65536:
         pytest.skip("grid line beyond the FP64 line capacity (plan creation rejects it)")
+    if c * g["nt"] > 8192:
+        pytest.skip("grid line beyond one workgroup's LDS (plan creation rejects it)")
     print(f"R kb c={c} K={K} {prec} fused={fused} {g}", flush=True)
     shape = (g["n1"], g["n2"], g["nt"]) if g["n2"] > 1 else (g["n1"], g["nt"])
     p = inputs.random_array(shape, 500 + gi)
