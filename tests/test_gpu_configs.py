@@ -140,6 +140,43 @@ def test_config3_properties(config3):
     assert torch.isfinite(f0).all()
 
 
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("f64", 1e-12)])
+def test_config3_transpose_pairs(config3, prec, tol):
+    """R^T and A at full size (the kernels of the benchmark's shape) against R
+    and A^T through the transpose identities <R p, q> = <p, R^T q> and
+    <A f, p'> = <f, A^T p'>.  The test vectors are q = R p + noise and
+    p' = A q + noise, so each inner product is close to the product of the
+    norms it is measured against (a random q would leave it sqrt(N) times
+    smaller and the bound loose)."""
+    p, g, _ = config3
+    say(f"config3 transpose pairs {prec}")
+    plan = plan_for(g, prec)
+    gen = torch.Generator(device=DEV).manual_seed(31)
+
+    def noisy(x):
+        n = torch.randn(x.shape, device=DEV, dtype=x.dtype, generator=gen)
+        return (x + 0.1 * x.std() * n).contiguous()
+
+    def rel_gap(a, b, u, v):
+        return abs(a - b) / (torch.linalg.vector_norm(u) * torch.linalg.vector_norm(v)).item()
+
+    P = dev(p, prec)
+    RP = plan.reconstruct(P).clone()
+    Q = noisy(RP)
+    lhs = torch.sum(RP.double() * Q.double()).item()
+    rhs = torch.sum(P.double() * plan.reconstruct_adjoint(Q).double()).item()
+    gap = rel_gap(lhs, rhs, RP.double(), Q.double())
+    say(f"  <Rp,q> vs <p,R^T q>: {gap:.2e}")
+    assert gap <= tol
+    AQ = plan.forward(Q).clone()
+    P2 = noisy(AQ)
+    lhs = torch.sum(AQ.double() * P2.double()).item()
+    rhs = torch.sum(Q.double() * plan.forward_adjoint(P2).double()).item()
+    gap = rel_gap(lhs, rhs, AQ.double(), P2.double())
+    say(f"  <Aq,p'> vs <q,A^T p'>: {gap:.2e}")
+    assert gap <= tol
+
+
 # ---------------------------------------------------------------------------
 # config 4
 
