@@ -145,6 +145,27 @@ __device__ __forceinline__ void dft_pow2(cx<T>* v) {
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, d13);
     v[3] = csub(d02, d13);
+  } else if constexpr (R == 16) {
+    // two 8-point DFTs of the even and odd samples, odd outputs turned by
+    // exp(-2 pi i d / 16)
+    cx<T> e[8], o[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      e[r] = v[2 * r];
+      o[r] = v[2 * r + 1];
+    }
+    dft_pow2<T, 8>(e);
+    dft_pow2<T, 8>(o);
+    const T c1 = T(0.92387953251128675612818318939678829), s1 = T(0.38268343236508977172845998403039887);
+    const T h = T(0.70710678118654752440084436210484904);
+    const T cs[8] = {T(1), c1, h, s1, T(0), -s1, -h, -c1};
+    const T sn[8] = {T(0), s1, h, c1, T(1), c1, h, s1};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const cx<T> t = mk(o[d].x * cs[d] + o[d].y * sn[d], o[d].y * cs[d] - o[d].x * sn[d]);
+      v[d] = cadd(e[d], t);
+      v[d + 8] = csub(e[d], t);
+    }
   } else {
     static_assert(R == 8, "radix");
     const T h = T(0.70710678118654752440084436210484904);
@@ -497,16 +518,20 @@ __device__ void fft_lds_p2_src_sink(cx<T>* buf, const FftDesc& d, const cx<T>* _
 
 // Radix plan of 2^E points known at compile time, by the host plan's rule:
 // radix 8 while it divides, ending in 4 (E mod 3 = 2), 4 and 4 (E mod 3 = 1,
-// E >= 4), or 2 (E = 1).  With every length and stage a constant, the stage
-// loops, index shifts and output positions fold at compile time.
-template <int E>
+// E >= 4), or 2 (E = 1).  With L16 the plan of 2^(E-4) points is followed by
+// one radix-16 stage instead (used where the output order is the kernel's
+// own, not the host's permutation table).  With every length and stage a
+// constant, the stage loops, index shifts and output positions fold at
+// compile time.
+template <int E, bool L16 = false>
 struct P2Plan {
   static constexpr int n8 = E / 3, rem = E % 3;
-  static constexpr int nst = rem == 0 ? n8 : n8 + 1;
+  static constexpr int nst = L16 ? P2Plan<(L16 ? E - 4 : 1)>::nst + 1 : rem == 0 ? n8 : n8 + 1;
   static constexpr int rad(int s) {
+    if (L16) return s + 1 == nst ? 16 : P2Plan<(L16 ? E - 4 : 1)>::rad(s);
     return rem == 0 ? 8 : rem == 2 ? (s < n8 ? 8 : 4) : n8 > 0 ? (s < n8 - 1 ? 8 : 4) : 2;
   }
-  static constexpr int lbits(int s) { return rad(s) == 8 ? 3 : rad(s) == 4 ? 2 : 1; }
+  static constexpr int lbits(int s) { return rad(s) == 16 ? 4 : rad(s) == 8 ? 3 : rad(s) == 4 ? 2 : 1; }
   // log2 of the span Li that stage s works on
   static constexpr int lspan(int s) { return s == 0 ? E : lspan(s - 1) - lbits(s - 1); }
   // natural index of the output at position pos (digit reversal of the plan)
@@ -523,16 +548,22 @@ struct P2Plan {
 };
 static_assert(P2Plan<10>::nst == 4 && P2Plan<10>::rad(0) == 8 && P2Plan<10>::rad(2) == 4, "plan of 1024");
 static_assert(P2Plan<8>::nst == 3 && P2Plan<8>::rad(2) == 4 && P2Plan<9>::rad(2) == 8, "plans of 256, 512");
+// the fused type-2 kernel ends a plan in one radix-16 stage where that saves
+// a stage against the host plan's two radix-4 stages: E mod 3 = 1, E >= 7
+constexpr bool p2_l16(int e) { return e % 3 == 1 && e >= 7; }
+static_assert(P2Plan<10, true>::nst == 3 && P2Plan<10, true>::rad(1) == 8 && P2Plan<10, true>::rad(2) == 16 &&
+                  P2Plan<7, true>::nst == 2 && P2Plan<7, true>::rad(0) == 8 && P2Plan<7, true>::lspan(1) == 4,
+              "plans ending in radix 16");
 
 // Stages S .. nst - 2 (twiddled, in place) of the compile-time plan of 2^E
 // points on nb lines of stride 2^E, one block barrier after each.
-template <typename T, int E, int S>
+template <typename T, int E, int S, bool L16 = false>
 __device__ __forceinline__ void p2_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int nb) {
-  using Pl = P2Plan<E>;
+  using Pl = P2Plan<E, L16>;
   if constexpr (S + 1 < Pl::nst) {
     fft_stage<T, Pl::rad(S), true, true>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
     __syncthreads();
-    p2_stages<T, E, S + 1>(buf, tw, nb);
+    p2_stages<T, E, S + 1, L16>(buf, tw, nb);
   }
 }
 
@@ -2196,14 +2227,15 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft2_pipe(StageArgs a) {
 
 // k_line_nufft2_pipe for m = 2^LM and nz = 2^LZ known at compile time (the
 // line group then holds 2^(11 - LM) lines): the same work, with the FFT
-// stages, their loops and the output positions fixed by P2Plan.  Four waves
-// per SIMD: at the five-wave register cap (96) the unrolled stages spill.
+// stages, their loops and the output positions fixed by P2Plan.  Bounded at
+// four waves per SIMD (128 registers): a five-wave cap (96) made several
+// instances spill, while those that need no more than 96 still run five.
 template <typename T, int TAPS, int LM, int LZ>
 __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
   const Inst& I = *a.inst[0];
   constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, lpw = 2048 / m;
-  using PM = P2Plan<LM>;
-  using PZ = P2Plan<LZ>;
+  using PM = P2Plan<LM, p2_l16(LM)>;
+  using PZ = P2Plan<LZ, p2_l16(LZ)>;
   static_assert(PM::rad(0) == 8 && PM::nst >= 2 && LZ <= LM, "pipelined first stage");
   const int sub = m >> 3, lsub = __builtin_ctz((unsigned)sub);
   const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
@@ -2250,7 +2282,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
       for (int r = 0; r < 8; ++r) p[r * sub] = v[r];
     }
     __syncthreads();
-    p2_stages<T, LM, 1>(gp, twm, lpw);
+    p2_stages<T, LM, 1, p2_l16(LM)>(gp, twm, lpw);
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
     auto sink = [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
@@ -2266,7 +2298,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
                                              [&](int e, cx<T> v) { fz[e] = cconj(v); });
     __syncthreads();
     cx<T>* out = outb + (size_t)line0 * nz;
-    p2_stages<T, LZ, 0>(fz, twz, lpw);
+    p2_stages<T, LZ, 0, p2_l16(LZ)>(fz, twz, lpw);
     fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(fz, nz, lpw, nz, 1, [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       if (b >= nl) return;
@@ -2352,8 +2384,8 @@ __global__ __launch_bounds__(kBlock) void k_line_nufft1(StageArgs a) {
 template <typename T, int TAPS, int LM, int LZ>
 __global__ __launch_bounds__(kBlock, 5) void k_line_nufft1_c(StageArgs a) {
   constexpr int m = 1 << LM, nz = 1 << LZ;
-  using PM = P2Plan<LM>;
-  using PZ = P2Plan<LZ>;
+  using PM = P2Plan<LM>;  // (no radix-16 last stage: it spills at this kernel's register
+  using PZ = P2Plan<LZ>;  // cap in the grid FFT and gained nothing in the depth FFT)
   static_assert(PM::nst >= 2 && PZ::nst >= 2, "two or more stages");
   PAT_FOR_EACH_ITEM(a)
   const int nt = I.nt;
