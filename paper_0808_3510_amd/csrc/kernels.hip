@@ -548,9 +548,11 @@ struct P2Plan {
 };
 static_assert(P2Plan<10>::nst == 4 && P2Plan<10>::rad(0) == 8 && P2Plan<10>::rad(2) == 4, "plan of 1024");
 static_assert(P2Plan<8>::nst == 3 && P2Plan<8>::rad(2) == 4 && P2Plan<9>::rad(2) == 8, "plans of 256, 512");
-// the fused type-2 kernel ends a plan in one radix-16 stage where that saves
-// a stage against the host plan's two radix-4 stages: E mod 3 = 1, E >= 7
-constexpr bool p2_l16(int e) { return e % 3 == 1 && e >= 7; }
+// the fused type-2 kernel ends its transforms in one radix-16 stage (which
+// has no twiddles): the depth FFT from 64 points on, the grid FFT where the
+// plan before it still opens with the radix-8 stage its pipeline needs
+constexpr bool p2_l16_z(int e) { return e >= 6; }
+constexpr bool p2_l16_m(int e) { return e >= 9; }
 static_assert(P2Plan<10, true>::nst == 3 && P2Plan<10, true>::rad(1) == 8 && P2Plan<10, true>::rad(2) == 16 &&
                   P2Plan<7, true>::nst == 2 && P2Plan<7, true>::rad(0) == 8 && P2Plan<7, true>::lspan(1) == 4,
               "plans ending in radix 16");
@@ -2234,8 +2236,8 @@ template <typename T, int TAPS, int LM, int LZ>
 __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
   const Inst& I = *a.inst[0];
   constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, lpw = 2048 / m;
-  using PM = P2Plan<LM, p2_l16(LM)>;
-  using PZ = P2Plan<LZ, p2_l16(LZ)>;
+  using PM = P2Plan<LM, p2_l16_m(LM)>;
+  using PZ = P2Plan<LZ, p2_l16_z(LZ)>;
   static_assert(PM::rad(0) == 8 && PM::nst >= 2 && LZ <= LM, "pipelined first stage");
   const int sub = m >> 3, lsub = __builtin_ctz((unsigned)sub);
   const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
@@ -2282,7 +2284,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
       for (int r = 0; r < 8; ++r) p[r * sub] = v[r];
     }
     __syncthreads();
-    p2_stages<T, LM, 1, p2_l16(LM)>(gp, twm, lpw);
+    p2_stages<T, LM, 1, p2_l16_m(LM)>(gp, twm, lpw);
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
     auto sink = [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
@@ -2298,7 +2300,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
                                              [&](int e, cx<T> v) { fz[e] = cconj(v); });
     __syncthreads();
     cx<T>* out = outb + (size_t)line0 * nz;
-    p2_stages<T, LZ, 0, p2_l16(LZ)>(fz, twz, lpw);
+    p2_stages<T, LZ, 0, p2_l16_z(LZ)>(fz, twz, lpw);
     fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(fz, nz, lpw, nz, 1, [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       if (b >= nl) return;
