@@ -121,6 +121,30 @@ def test_plane_wave_closed_form(n, dx):
         np.testing.assert_allclose(f, np.broadcast_to(expect, f.shape), atol=1e-12)
 
 
+@pytest.mark.parametrize("vs,dt,dz,nt,nz", [(1.3, 0.4, 1.0, 160, 64), (0.8, 0.5, 0.7, 192, 96)])
+def test_dalembert_weight_scale(vs, dt, dz, nt, nz):
+    """Scale of the Jacobian weight ``2 vs (dt/dz) |K_z|/|K|`` (Section 2
+    eq. inv with the grid scalings of Section 4 eq. fft-0) at vs != 1 and
+    dt != dz.  For an x-constant initial pressure f(y) inside the depth window
+    the trace is the 1D d'Alembert solution ``p(t) = f(vs t) / 2``; only the
+    line k = 0 is non-zero, its nodes are ``l (nt dt vs) / (nz dz)`` and R
+    returns the depth samples of f minus their mean (the l = 0 plane).  A
+    Gaussian of width 3 dz centred in the window is band-limited and
+    vanishes at both ends to below 1e-20, and ``vs dt < dz`` keeps the
+    time samples finer than the depth grid, so the sums are exact to
+    rounding.  Dropping vs, inverting dt/dz or the factor 2 fails this."""
+    n1, n2 = 4, 2
+    g = _geom(n1, n2, nt, nz, dx=1.0, dt=dt, dz=dz, vs=vs)
+    c0, sig = 0.5 * nz * dz, 3.0 * dz
+    f = lambda y: np.exp(-(y - c0) ** 2 / (2 * sig * sig))  # noqa: E731
+    assert vs * nt * dt >= nz * dz and vs * dt < dz  # the trace covers the window
+    h = 0.5 * f(vs * dt * np.arange(nt))
+    p = np.broadcast_to(h, (n1, n2, nt)).copy()
+    out = recon.reconstruct(p, g)
+    fq = f(dz * np.arange(nz))
+    np.testing.assert_allclose(out, np.broadcast_to(fq - fq.mean(), out.shape), rtol=0, atol=1e-10)
+
+
 def _hermitian_dft(f):
     return np.fft.fftn(f)
 
