@@ -127,6 +127,50 @@ def spectrum_lines(p, g, lines):
     return out
 
 
+def adjoint_lines(q, g, lines):
+    """The transverse spectrum of R^T q on selected signed lines, before the
+    real part: ``X[k, n] = (1/nz) sum_l exp(+2 pi i nu_{k,l} n / nt) W_{k,l}
+    Q[k, l]`` with ``Q`` the DFT of ``q`` over all axes; returns
+    ``(len(lines), nt)``.  (R^T q itself is ``Re(IDFT_x(X))``, so the DFT over
+    x of R^T q at k is ``(X[k] + conj(X[-k])) / 2``.)"""
+    q3, _ = _as3(q, g)
+    Q = np.fft.fftn(q3, axes=(0, 1, 2))
+    l = int_freqs(g["nz"])
+    out = np.empty((len(lines), g["nt"]), dtype=np.complex128)
+    for i, (k1, k2) in enumerate(lines):
+        E = _phase(nodes(k1, k2, l, g), g["nt"])           # (nz, nt)
+        out[i] = ((Q[k1 % g["n1"], k2 % g["n2"], :] * weights(k1, k2, l, g)) @ np.conj(E)) / g["nz"]
+    return out
+
+
+def forward_lines(f, g, lines):
+    """The transverse spectrum of A f on selected signed lines, before the
+    real part: ``P[k, n] = (1/nz) sum_l F[k, l] cos(2 pi nu+_{k,l} n / nt)``,
+    ``(len(lines), nt)``."""
+    f3, _ = _as3(f, g)
+    F = np.fft.fftn(f3, axes=(0, 1, 2))
+    l = int_freqs(g["nz"])
+    out = np.empty((len(lines), g["nt"]), dtype=np.complex128)
+    for i, (k1, k2) in enumerate(lines):
+        C = _cos(node_plus(k1, k2, l, g), g["nt"])
+        out[i] = (F[k1 % g["n1"], k2 % g["n2"], :] @ C) / g["nz"]
+    return out
+
+
+def forward_adjoint_lines(p, g, lines):
+    """The spectrum of A^T p on selected signed lines, before the real part:
+    ``Y[k, l] = sum_n cos(2 pi nu+_{k,l} n / nt) P[k, n]`` with ``P`` the DFT of
+    ``p`` over x, ``(len(lines), nz)``; the DFT over all axes of A^T p at
+    ``(k, l)`` is ``(Y[k, l] + conj(Y[-k, -l])) / 2``."""
+    P = transverse_dft(p, g)
+    l = int_freqs(g["nz"])
+    out = np.empty((len(lines), g["nz"]), dtype=np.complex128)
+    for i, (k1, k2) in enumerate(lines):
+        C = _cos(node_plus(k1, k2, l, g), g["nt"])
+        out[i] = C @ P[k1 % g["n1"], k2 % g["n2"], :]
+    return out
+
+
 def reconstruct(p, g):
     """R: detector data ``p`` -> image ``f`` (direct Fourier reconstruction)."""
     _, flat = _as3(p, g)

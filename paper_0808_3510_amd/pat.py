@@ -235,8 +235,7 @@ class Plan:
     def _check(self, x: torch.Tensor, last: int, what: str) -> torch.Tensor:
         if not isinstance(x, torch.Tensor):
             raise TypeError(f"{what} must be a torch tensor")
-        if x.device != self.device and not (x.device.type == self.device.type and
-                                            (self.device.index is None or x.device.index == self.device.index)):
+        if not self._on_device(x):
             raise ValueError(f"{what} is on {x.device}, plan on {self.device}")
         if x.dtype != self.dtype:
             raise TypeError(f"{what} must be {self.dtype}, got {x.dtype}")
@@ -273,19 +272,45 @@ class Plan:
         """A^T: data-shaped -> image-shaped."""
         return self._call(pat_forward_adjoint, p, self.nt, self.nz, out)
 
+    def _on_device(self, x: torch.Tensor) -> bool:
+        return x.device.type == self.device.type and (self.device.index is None or
+                                                      x.device.index == self.device.index)
+
+    def _check_lines(self, x, shape, dtype, what: str) -> torch.Tensor:
+        """A line-stage array: exact dtype, shape, device and contiguity
+        (the C ABI takes no sizes, so nothing short or misplaced may reach it)."""
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{what} must be a torch tensor")
+        if x.dtype != dtype:
+            raise ValueError(f"{what} must be {dtype}, got {x.dtype}")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{what} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+        if not self._on_device(x):
+            raise ValueError(f"{what} is on {x.device}, plan on {self.device}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        return x
+
+    def _grid_spec(self):
+        if self.precision == "bf16grid":
+            return (self.lines, self.m, 2), torch.bfloat16
+        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+        return (self.lines, self.m), cdt
+
+    def _values_spec(self):
+        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+        return (self.lines, self.nz), cdt
+
     def nufft2_lines(self, grid: torch.Tensor, out=None) -> torch.Tensor:
         """Stage a3 alone: grid ``(lines, m)`` complex (``(lines, m, 2)``
         bfloat16 for the bf16 grid) -> ``(lines, nz)`` complex."""
-        if self.precision == "bf16grid":
-            ok = grid.dtype == torch.bfloat16 and tuple(grid.shape) == (self.lines, self.m, 2)
-        else:
-            cdt = torch.complex128 if self.precision == "f64" else torch.complex64
-            ok = grid.dtype == cdt and tuple(grid.shape) == (self.lines, self.m)
-        if not ok or not grid.is_contiguous() or grid.device.type != self.device.type:
-            raise ValueError("grid has the wrong dtype, shape, device or layout")
-        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
+        gshape, gdt = self._grid_spec()
+        vshape, vdt = self._values_spec()
+        self._check_lines(grid, gshape, gdt, "grid")
         if out is None:
-            out = torch.empty((self.lines, self.nz), dtype=cdt, device=self.device)
+            out = torch.empty(vshape, dtype=vdt, device=self.device)
+        else:
+            self._check_lines(out, vshape, vdt, "out")
         pat_nufft2_lines(self.ptr, grid.data_ptr(), out.data_ptr(), _stream(self.device))
         return out
 
@@ -293,14 +318,13 @@ class Plan:
         """Spreading alone, the adjoint of :meth:`nufft2_lines`: values
         ``(lines, nz)`` complex -> grid ``(lines, m)`` complex (``(lines, m, 2)``
         bfloat16 for the bf16 grid)."""
-        cdt = torch.complex128 if self.precision == "f64" else torch.complex64
-        if values.dtype != cdt or tuple(values.shape) != (self.lines, self.nz) or not values.is_contiguous():
-            raise ValueError("values have the wrong dtype, shape or layout")
+        gshape, gdt = self._grid_spec()
+        vshape, vdt = self._values_spec()
+        self._check_lines(values, vshape, vdt, "values")
         if out is None:
-            if self.precision == "bf16grid":
-                out = torch.empty((self.lines, self.m, 2), dtype=torch.bfloat16, device=self.device)
-            else:
-                out = torch.empty((self.lines, self.m), dtype=cdt, device=self.device)
+            out = torch.empty(gshape, dtype=gdt, device=self.device)
+        else:
+            self._check_lines(out, gshape, gdt, "out")
         pat_nufft1_lines(self.ptr, values.data_ptr(), out.data_ptr(), _stream(self.device))
         return out
 
@@ -323,9 +347,14 @@ def reconstruct_batched(plans, ps, outs=None, ws=None):
         pl._check(p, pl.nt, "input")
     if outs is None:
         outs = [pl._out(p, pl.nz) for pl, p in zip(plans, ps)]
+    elif len(outs) != len(plans):
+        raise ValueError("one output per plan")
+    else:
+        for pl, o in zip(plans, outs):
+            pl._check(o, pl.nz, "output")
     ptrs = [pl.ptr for pl in plans]
     need = pat_batched_workspace_size(ptrs)
-    if ws is None or ws.numel() < need:
+    if ws is None or ws.numel() < need or not plans[0]._on_device(ws) or not ws.is_contiguous():
         ws = torch.empty(need, dtype=torch.uint8, device=plans[0].device)
     pat_reconstruct_batched(ptrs, [p.data_ptr() for p in ps], [o.data_ptr() for o in outs], ws.data_ptr(),
                             _stream(plans[0].device))

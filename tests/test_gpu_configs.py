@@ -42,16 +42,22 @@ def plan_for(g, prec):
                     device=DEV)
 
 
-def sampled_line_error(f_gpu, p, g, lines):
-    """relL2 between the spectrum of the GPU output on `lines` and the
-    Hermitian part of the oracle's spectrum there."""
+def sampled_line_spectra(f_gpu, p, g, lines):
+    """The spectrum of the GPU output on `lines` and the Hermitian part of the
+    oracle's spectrum there, ``(len(lines), nz)`` each."""
     n1, n2, nz = g["n1"], g["n2"], g["nz"]
     D = np.fft.fftn(f_gpu.astype(np.float64).reshape(n1, n2, nz))
     ora = recon.spectrum_lines(p, g, lines)
     mir = recon.spectrum_lines(p, g, [(-a, -b) for a, b in lines])
     lneg = (-np.arange(nz)) % nz
     got = np.array([D[a % n1, b % n2] for a, b in lines])
-    exp = 0.5 * (ora + np.conj(mir[:, lneg]))
+    return got, 0.5 * (ora + np.conj(mir[:, lneg]))
+
+
+def sampled_line_error(f_gpu, p, g, lines):
+    """relL2 between the spectrum of the GPU output on `lines` and the
+    Hermitian part of the oracle's spectrum there."""
+    got, exp = sampled_line_spectra(f_gpu, p, g, lines)
     return relerr(got, exp)
 
 
@@ -107,19 +113,47 @@ def config3():
     p, g, balls = inputs.planar_case(256, 32, 1003, noise=1e-3)
     rng = inputs.rng(303)
     lines = [(0, 0), (128, 128), (128, 0), (0, 128), (-128, 5), (1, -1)]
-    lines += [(int(a), int(b)) for a, b in rng.integers(-128, 128, size=(26, 2))]
+    lines += [(int(a), int(b)) for a, b in rng.integers(-128, 128, size=(506, 2))]
     return p, g, lines
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-9), ("bf16grid", 1e-2)])
 def test_config3_sampled_lines(config3, prec, tol):
+    """R at full size on 512 sampled output lines, element by element, with
+    the l = 0 plane (weight 0) and the depth-Nyquist plane on their own."""
     p, g, lines = config3
     say(f"config3 {prec}")
     f = plan_for(g, prec).reconstruct(dev(p, prec))
     torch.cuda.synchronize()
-    err = sampled_line_error(f.cpu().numpy(), p, g, lines)
-    say(f"  sampled-line relL2 = {err:.3e}")
-    assert err < tol
+    got, exp = sampled_line_spectra(f.cpu().numpy(), p, g, lines)
+    err = relerr(got, exp)
+    mx = np.abs(got - exp).max() / np.abs(exp).max()
+    h = g["nz"] // 2
+    nyq = relerr(got[:, h], exp[:, h])
+    say(f"  512 sampled lines: relL2 {err:.3e}, max {mx:.3e}, Nyquist plane {nyq:.3e}")
+    assert err < tol and mx < tol and nyq < tol
+    assert np.abs(got[:, 0]).max() <= tol * np.abs(exp).max()
+
+
+@pytest.mark.parametrize("op", ["reconstruct_adjoint", "forward"])
+def test_config3_type1_sampled_lines(config3, op):
+    """The fused type-1 kernel at the benchmark's size (R^T, A) on 128 sampled
+    lines of the output, element by element against the oracle's sums."""
+    p, g, lines = config3
+    say(f"config3 {op} sampled lines")
+    n1, n2, nt = g["n1"], g["n2"], g["nt"]
+    q = inputs.random_array((n1, n2, g["nz"]), 333)
+    out = getattr(plan_for(g, "f32"), op)(dev(q)).cpu().double().numpy()
+    sel = lines[:128]
+    fn = recon.adjoint_lines if op == "reconstruct_adjoint" else recon.forward_lines
+    X, Xm = fn(q, g, sel), fn(q, g, [(-a, -b) for a, b in sel])
+    D = np.fft.fft2(out, axes=(0, 1))
+    got = np.array([D[a % n1, b % n2] for a, b in sel])
+    exp = 0.5 * (X + np.conj(Xm))
+    err = relerr(got, exp)
+    mx = np.abs(got - exp).max() / np.abs(exp).max()
+    say(f"  relL2 {err:.3e}, max {mx:.3e}")
+    assert got.shape == (128, nt) and err < 1e-5 and mx < 1e-5
 
 
 def test_config3_properties(config3):

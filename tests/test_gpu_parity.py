@@ -225,3 +225,26 @@ def test_fused_adjoint_sizes_match_oracle(op, g):
     y = getattr(plan, op)(to_dev(x, "f32"))
     torch.cuda.synchronize()
     assert relerr(y.cpu().double().numpy(), getattr(recon, op)(x, g)) < TOL["f32"]
+
+
+def test_line_stage_wrappers_reject_bad_buffers():
+    """The stand-alone stage wrappers check every buffer before calling in:
+    a CPU tensor, a short output or a wrong dtype raise before any launch."""
+    g = SMALL[0]
+    plan = make_plan(g, "f32")
+    grid = torch.zeros((plan.lines, plan.m), dtype=torch.complex64, device=DEV)
+    vals = torch.zeros((plan.lines, plan.nz), dtype=torch.complex64, device=DEV)
+    with pytest.raises(ValueError):
+        plan.nufft2_lines(grid.cpu())
+    with pytest.raises(ValueError):
+        plan.nufft2_lines(grid, out=torch.empty((plan.lines, plan.nz - 1), dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        plan.nufft2_lines(grid, out=torch.empty((plan.lines, plan.nz), dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        plan.nufft1_lines(vals.cpu())
+    with pytest.raises(ValueError):
+        plan.nufft1_lines(vals, out=torch.empty((plan.lines, plan.m - 2), dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        plan.nufft1_lines(vals.to(torch.complex128))
+    # the checked calls still run
+    assert plan.nufft1_lines(vals).abs().max().item() == 0.0

@@ -64,11 +64,15 @@ KB_GEOS = GEOS[:2] + [dict(n1=16, n2=1, nt=512, nz=64, dx=1 / 16, dt=1 / 512, dz
 @pytest.mark.parametrize("gi", range(len(KB_GEOS)))
 def test_kaiser_bessel_oversampling_sweep(fused, prec, c, K, gi):
     g = KB_GEOS[gi]
-    if prec == "f64" and c * g["nt"] * 16 > 65536:
-        pytest.skip("grid line beyond the FP64 line capacity (plan creation rejects it)")
-    if c * g["nt"] > 8192:
-        pytest.skip("grid line beyond one workgroup's LDS (plan creation rejects it)")
     print(f"R kb c={c} K={K} {prec} fused={fused} {g}", flush=True)
+    if c * g["nt"] * (16 if prec == "f64" else 8) > 65536:
+        # a grid line beyond one workgroup's line capacity: plan creation
+        # refuses it before anything runs
+        with pytest.raises(pat.PatError) as ei:
+            pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K,
+                     precision=prec, device="cuda")
+        assert ei.value.status == 2
+        return
     shape = (g["n1"], g["n2"], g["nt"]) if g["n2"] > 1 else (g["n1"], g["nt"])
     p = inputs.random_array(shape, 500 + gi)
     expect = recon.reconstruct_with(p, g, "kb", c, K)

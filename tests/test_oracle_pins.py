@@ -193,6 +193,29 @@ def test_spectrum_lines_matches_full_spectrum():
         np.testing.assert_allclose(got[i], full[k1 % 16, k2 % 16], rtol=1e-13, atol=1e-9)
 
 
+def test_operator_lines_match_full_operators():
+    """The per-line forms of R^T, A and A^T (used to check large outputs line
+    by line) against the full operators: the DFT of the real output on a line
+    is the Hermitian part of the line's complex spectrum."""
+    g = _geom(12, 10, 24, 14, dx=0.9, dt=0.7, dz=1.1, vs=1.2)
+    rg = inputs.rng(61)
+    q = rg.standard_normal((12, 10, 14))
+    p = rg.standard_normal((12, 10, 24))
+    lines = [(0, 0), (3, -5), (-6, 4), (6, -5), (1, 1), (5, 0)]
+    mir = [(-a, -b) for a, b in lines]
+    lneg = (-np.arange(14)) % 14
+    D = np.fft.fft2(recon.reconstruct_adjoint(q, g), axes=(0, 1))
+    X, Xm = recon.adjoint_lines(q, g, lines), recon.adjoint_lines(q, g, mir)
+    D2 = np.fft.fft2(recon.forward(q, g), axes=(0, 1))
+    P, Pm = recon.forward_lines(q, g, lines), recon.forward_lines(q, g, mir)
+    D3 = np.fft.fftn(recon.forward_adjoint(p, g))
+    Y, Ym = recon.forward_adjoint_lines(p, g, lines), recon.forward_adjoint_lines(p, g, mir)
+    for i, (a, b) in enumerate(lines):
+        np.testing.assert_allclose(D[a % 12, b % 10], 0.5 * (X[i] + np.conj(Xm[i])), rtol=0, atol=1e-11)
+        np.testing.assert_allclose(D2[a % 12, b % 10], 0.5 * (P[i] + np.conj(Pm[i])), rtol=0, atol=1e-11)
+        np.testing.assert_allclose(D3[a % 12, b % 10], 0.5 * (Y[i] + np.conj(Ym[i][lneg])), rtol=0, atol=1e-11)
+
+
 def test_reconstruction_shift_equivariance_and_real():
     p, g, _ = inputs.planar_case(16, 3, 21, noise=1e-3)
     f = recon.reconstruct(p, g)
