@@ -154,6 +154,22 @@ pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream);
  * p, f: device arrays as described above.  ws: workspace_bytes. */
 pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, void* stream);
 
+/* R as pat_reconstruct, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument, and the call allocates nothing.  Its
+ * workspace is a static array of the library, 64 MiB per device, reserved
+ * when the library's code is first loaded on that device and held until the
+ * process ends; its address is looked up once per device.  The fused line
+ * path needs lines*(nt + nz) complex elements of it (256-byte aligned parts),
+ * the staged path pat_plan_sizes().workspace_bytes; a plan needing more gets
+ * PAT_ERR_UNSUPPORTED before anything is enqueued (FP32 fits up to about
+ * 128^2 x 256 -> 128^3; 256^2 x 512 does not).  Every call on a device shares
+ * that device's array and leaves its contents behind (nothing in it needs
+ * clearing: each call writes every part it reads).  Calls that overlap on one
+ * device, on different streams or host threads, race on the array and must
+ * be serialised by the caller.  Results equal pat_reconstruct's. */
+pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, void* f, void* stream);
+
 /* R^T: the exact transpose of R for the real inner product (type-1 NUFFT
  * spreading; the gradient of R).  f-shaped input -> p-shaped output. */
 pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, void* p, void* ws, void* stream);

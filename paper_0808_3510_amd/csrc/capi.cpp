@@ -77,25 +77,38 @@ pat_status check_plan(const pat_plan* p) {
   return PAT_OK;
 }
 
-pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, void* stream) {
+// Checks shared by the single-plan operators (workspace aside).
+pat_status check_call(pat_plan* plan, pat::Op op, const void* in, void* out) {
   pat_status s = check_plan(plan);
   if (s != PAT_OK) return s;
   if (!aligned16(in) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
-  if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
   if (op != pat::OP_R && plan->inst.kind != PAT_INTERP_KB)
     return set_err(PAT_ERR_UNSUPPORTED, "only the reconstruction runs with an interp other than PAT_INTERP_KB");
   if ((op == pat::OP_RT || op == pat::OP_A) && !plan->spread_ok)
     return set_err(PAT_ERR_UNSUPPORTED, "nz too large for the spreading lists of a depth line in LDS");
+  return PAT_OK;
+}
+
+// Enqueues one operator of one plan; h: the host descriptor (its workspace
+// offsets place the stages' arrays in ws).
+pat_status enqueue(pat_plan* plan, const pat::Inst& h, pat::Op op, const void* in, void* out, void* ws, void* stream,
+                   pat::StageTimer* tm) {
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
   const pat::Inst* dd[1] = {d};
   const void* ins[1] = {in};
   void* outs[1] = {out};
   void* wss[1] = {ws};
   const void* hp[1] = {plan->blob.data() + plan->off_poly};
-  hipError_t e = pat::run_op(plan->prec, op, 1, &plan->inst, dd, hp, ins, outs, wss, nullptr,
-                             static_cast<hipStream_t>(stream), timer_of(plan));
+  hipError_t e = pat::run_op(plan->prec, op, 1, &h, dd, hp, ins, outs, wss, nullptr, static_cast<hipStream_t>(stream), tm);
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
+}
+
+pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, void* stream) {
+  pat_status s = check_call(plan, op, in, out);
+  if (s != PAT_OK) return s;
+  if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  return enqueue(plan, plan->inst, op, in, out, ws, stream, timer_of(plan));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -159,6 +172,29 @@ pat_status pat_forward(pat_plan* plan, const void* f, void* p, void* ws, void* s
 
 pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws, void* stream) {
   return run(plan, pat::OP_AT, p, f, ws, stream);
+}
+
+pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, void* f, void* stream) {
+  pat_status s = check_call(plan, pat::OP_R, p, f);
+  if (s != PAT_OK) return s;
+  // the fused line path never stores the oversampled grid: its workspace is
+  // G and F only, packed back to back
+  pat::Inst h = plan->inst;
+  const size_t cs = pat::complex_bytes(plan->prec);
+  size_t need = plan->ws_bytes;
+  if (h.fused) {
+    h.off_u = h.off_f = (int64_t)align256((size_t)h.lines * h.nt * cs);
+    need = (size_t)h.off_f + align256((size_t)h.lines * h.nz * cs);
+  }
+  if (need > pat::kScratchBytes)
+    return set_err(PAT_ERR_UNSUPPORTED, "this plan needs " + std::to_string(need) +
+                                            " bytes of workspace; the static scratch of pat_reconstruct_noalloc holds " +
+                                            std::to_string(pat::kScratchBytes));
+  void* ws = nullptr;
+  hipError_t e = pat::scratch_buffer(&ws);
+  if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)");
+  // (no stage timing here: recording it creates events)
+  return enqueue(plan, h, pat::OP_R, p, f, ws, stream, nullptr);
 }
 
 pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes) {

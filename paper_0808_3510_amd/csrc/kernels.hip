@@ -2920,6 +2920,31 @@ hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void
   return hipErrorInvalidValue;
 }
 
+// Workspace of the allocation-free entry point: one array per device, held
+// until the process ends.  Host code never passes `scratch` itself (on the
+// host it is only a stand-in for the symbol): kernels get the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_buffer(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
 hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* vals, void* grid,
                       hipStream_t stream, StageTimer* timer) {
   switch (prec) {

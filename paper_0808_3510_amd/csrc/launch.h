@@ -35,4 +35,9 @@ hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void
 hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* vals,
                       void* grid, hipStream_t stream, StageTimer* timer);
 
+// Device address of the current device's kScratchBytes scratch array (a
+// file-scope __device__ array in kernels.hip), looked up with
+// hipGetSymbolAddress on the first call per device and cached.
+hipError_t scratch_buffer(void** ptr);
+
 }  // namespace pat

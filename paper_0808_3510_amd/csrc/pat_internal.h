@@ -14,6 +14,11 @@ constexpr int kMaxTaps = 64;     // 2cK
 constexpr double kMaxCutoff = 8.0;  // cut-off radius in sampling steps
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kNumCounters = 16; // persistent work counters per batched call
+// Bytes of the static per-device scratch array behind the allocation-free
+// entry point (pat_reconstruct_noalloc); a plan whose workspace needs more is
+// refused there.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;   // devices the scratch addresses are cached for
 constexpr size_t kLdsMax = 160 * 1024;  // LDS of one CDNA4 compute unit
 constexpr double kPi = 3.14159265358979323846264338327950288;
 // Degree of the per-tap polynomial that replaces the kernel evaluation

@@ -55,6 +55,7 @@ def lib():
             "pat_plan_sizes": (c_int32, [vp, POINTER(c_size_t), POINTER(c_size_t)]),
             "pat_plan_upload": (c_int32, [vp, vp, vp]),
             "pat_reconstruct": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_reconstruct_noalloc": (c_int32, [vp, vp, vp, vp]),
             "pat_reconstruct_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
             "pat_forward": (c_int32, [vp, vp, vp, vp, vp]),
             "pat_forward_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
@@ -112,6 +113,10 @@ def pat_plan_upload(plan: int, table: int, stream: int):
 
 def pat_reconstruct(plan, p, f, ws, stream):
     _check(lib().pat_reconstruct(plan, p, f, ws, stream))
+
+
+def pat_reconstruct_noalloc(plan, p, f, stream):
+    _check(lib().pat_reconstruct_noalloc(plan, p, f, stream))
 
 
 def pat_reconstruct_adjoint(plan, f, p, ws, stream):
@@ -259,6 +264,15 @@ class Plan:
     def reconstruct(self, p, out=None):
         """R: detector data -> image."""
         return self._call(pat_reconstruct, p, self.nt, self.nz, out)
+
+    def reconstruct_noalloc(self, p, out=None):
+        """R through the allocation-free entry point (the library's static
+        scratch instead of this plan's workspace; the output is still the
+        caller's)."""
+        self._check(p, self.nt, "input")
+        y = self._out(p, self.nz) if out is None else self._check(out, self.nz, "output")
+        pat_reconstruct_noalloc(self.ptr, p.data_ptr(), y.data_ptr(), _stream(self.device))
+        return y
 
     def reconstruct_adjoint(self, q, out=None):
         """R^T: image-shaped -> data-shaped."""
