@@ -1112,6 +1112,189 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Type-1 spreading of a line by one wavefront (FP32), node-parallel.
+//
+// The gather above runs cell by cell, so a cell where many nodes crowd (near
+// the smallest |nu| of a line with large |K_x|, up to ~40 nodes) holds up its
+// whole wavefront.  Here every lane owns a node instead and adds its TAPS
+// weighted values to cells j0 .. j0 + TAPS - 1, one tap per round.  The node
+// list is monotone, so lanes with equal first taps are contiguous; their
+// values are summed first (a segmented sum across the lanes, by DPP moves),
+// and only the last lane of each such segment adds the sum to its cell.  In a
+// round those writers hold distinct first taps, hence distinct cells, and the
+// rounds follow each other in program order: no atomics, and the summation
+// order is fixed (deterministic).  Every lane does the same work whatever the
+// node density: the cost of a crowd is the few extra scan steps of its
+// wavefront.
+
+// DPP move of a float across lanes: row_shr:d within rows of 16 lanes, or
+// row_bcast:15 / row_bcast:31.  Lanes whose source lies outside the pattern
+// read 0 (bound_ctrl); lanes of rows outside ROWS are not written, and every
+// use below selects them away.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, ROWS, 0xf, true));
+}
+
+// Segments of a key that is monotone over the 64 lanes (equal keys are
+// contiguous).  Bit k of `on` is set when the lane adds in step k of the
+// segmented inclusive sum: k = 0 .. 3 add lane L - 1, 2, 4, 8 of the same row of
+// 16 lanes (Hillis-Steele), k = 4 adds lane 15 of the row before (rows 1 and
+// 3), k = 5 adds lane 31 (rows 2 and 3); each only when that lane belongs to
+// the lane's own segment.  `use` (wave-uniform) marks the steps any lane
+// needs; after them the last lane of a segment (`tail`) holds its sum.
+struct WaveSeg {
+  unsigned on;
+  unsigned use;
+  bool tail;
+};
+
+__device__ __forceinline__ WaveSeg wave_segments(int key) {
+  const int L = (int)(threadIdx.x & 63);
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = L == 0 || prev != key;
+  const unsigned long long hm = __ballot(head);
+  const unsigned long long upto = L == 63 ? ~0ull : ((2ull << L) - 1ull);
+  const int ss = 63 - __clzll(hm & upto);  // first lane of the segment
+  const int r = L & 15;
+  unsigned f = 0;
+  f |= (r >= 1 && L - 1 >= ss) ? 1u : 0u;
+  f |= (r >= 2 && L - 2 >= ss) ? 2u : 0u;
+  f |= (r >= 4 && L - 4 >= ss) ? 4u : 0u;
+  f |= (r >= 8 && L - 8 >= ss) ? 8u : 0u;
+  f |= (((L >> 4) & 1) && ss <= (L & ~15) - 1) ? 16u : 0u;
+  f |= (L >= 32 && ss <= 31) ? 32u : 0u;
+  WaveSeg s;
+  s.on = f;
+  s.tail = L == 63 || ((hm >> (L + 1)) & 1ull);
+  unsigned u = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u |= __ballot((f >> k) & 1u) ? (1u << k) : 0u;
+  s.use = u;
+  return s;
+}
+
+template <int BIT, int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ void seg_step(const WaveSeg& s, float& x, float& y) {
+  if (s.use & BIT) {
+    const float tx = x + dpp_mov<CTRL, ROWS>(x);
+    const float ty = y + dpp_mov<CTRL, ROWS>(y);
+    const bool on = (s.on & BIT) != 0;
+    x = on ? tx : x;
+    y = on ? ty : y;
+  }
+}
+
+// Segmented inclusive sum of (x, y) over the lanes (see WaveSeg).
+__device__ __forceinline__ void seg_sum(const WaveSeg& s, float& x, float& y) {
+  seg_step<1, 0x111>(s, x, y);         // row_shr:1
+  seg_step<2, 0x112>(s, x, y);         // row_shr:2
+  seg_step<4, 0x114>(s, x, y);         // row_shr:4
+  seg_step<8, 0x118>(s, x, y);         // row_shr:8
+  seg_step<16, 0x142, 0xa>(s, x, y);   // row_bcast:15 into rows 1, 3
+  seg_step<32, 0x143, 0xc>(s, x, y);   // row_bcast:31 into rows 2, 3
+}
+
+// One pass of a wavefront's nodes (monotone first taps j0 over the active
+// lanes, which come first): cell (j0 + t) mod m of the LDS line G gains
+// w[t] v for t < TAPS.  Inactive lanes carry v = 0 and keys of their own.
+// When the active first taps span m cells or more, two segments could share
+// a cell modulo m; the writes of each round then go one lane at a time.
+template <int TAPS, bool P2>
+__device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bool act, int nact, cx<float> v,
+                                                 const float* w) {
+  const int L = (int)(threadIdx.x & 63);
+  const WaveSeg sg = wave_segments(act ? j0 : (0x40000000 + L));
+  const int jf = __shfl(j0, 0, 64), jl = __shfl(j0, nact - 1, 64);
+  const bool distinct = (jf > jl ? jf - jl : jl - jf) < m;
+  int r;  // j0 mod m
+  if constexpr (P2) {
+    r = j0 & (m - 1);
+  } else {
+    r = j0 % m;
+    r += r < 0 ? m : 0;
+  }
+  const bool wr = act && sg.tail;
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t) {
+    float x = w[t] * v.x, y = w[t] * v.y;
+    seg_sum(sg, x, y);
+    int c = r + t;
+    c -= c >= m ? m : 0;
+    if (distinct) {
+      if (wr) {
+        G[c].x += x;
+        G[c].y += y;
+      }
+    } else {
+      for (int k = 0; k < 64; ++k) {
+        if (wr && L == k) {
+          G[c].x += x;
+          G[c].y += y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    }
+    // the next round's reads come after this round's writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+}
+
+// Spreading of one line by one wavefront into the LDS line G (m cells,
+// zeroed here), the same sums as spread_line: lane L of batch k takes
+// |l| = q0 + 64k + L and both its nodes -nu+ and +nu+ (one pass each).  The
+// grid receives the conjugated values, as spread_line's put does.
+//   mode 0 (R^T): |l| = 1 .. nz/2, value conj(W exp(-i pi nu) scale) Qhat_l,
+//     l = sign(nu)|l|, the Nyquist pair both from Qhat_{-nz/2} at half weight;
+//   mode 1 (A): |l| = 0 .. nz/2, value (scale / 2) exp(i pi nu) (F_l + F_-l)
+//     (a single term at l = 0 and -nz/2).
+// fget(l_index) reads the line's depth spectrum (DFT order).
+template <int TAPS, bool P2, typename Fget>
+__device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs& a, int line, int mode, int m, int nz,
+                                                 cx<float>* G, Fget fget) {
+  const int L = (int)(threadIdx.x & 63);
+  float4* G4 = reinterpret_cast<float4*>(G);
+  for (int e = L; e < m / 2; e += 64) G4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const int half = nz / 2;
+  const int q0 = mode == 0 ? 1 : 0;
+  const int nq = half - q0 + 1;
+  const double Ak = line_ak(I, line);
+  const double wsc = I.wcoef * I.scale;
+  for (int base = 0; base < nq; base += 64) {
+    const int nact = min(64, nq - base);
+    const bool act = L < nact;
+    const int la = act ? q0 + base + L : q0;
+    const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
+    const cx<float> ph = phase_mpi<float>(nup);
+    cx<float> qp, qm;
+    double cf;
+    if (mode == 0) {
+      const bool nyq = la == half;
+      qp = fget(nyq ? half : la);
+      qm = fget(nyq ? half : nz - la);
+      cf = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
+    } else {
+      cx<float> q = fget(la);
+      if (la != 0 && la != half) q = cadd(q, fget(nz - la));
+      qp = qm = q;
+      cf = 0.5 * I.scale;
+    }
+    const float cff = act ? (float)cf : 0.f;
+    const cx<float> vals[2] = {cscl(cmul(cconj(qp), ph), cff), cscl(cmul(cconj(qm), cconj(ph)), cff)};
+#pragma unroll
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      const double xc = I.c * (sgn ? -nup : nup);
+      const double f = floor(xc - I.ck);
+      const float x = (float)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
+      float w[TAPS];
+      tap_weights_pairs<float, TAPS>(a, x, w);
+      spread_pass_wave<TAPS, P2>(G, m, (int)f + 1, act, nact, vals[sgn], w);
+    }
+  }
+}
+
 extern __shared__ __align__(16) unsigned char pat_smem[];
 
 // With a work counter, thread 0 takes the next item and hands it to the
@@ -2446,6 +2629,93 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft1_c(StageArgs a) {
   PAT_END_ITEM
 }
 
+// The fused type-1 kernel with wavefront spreading (FP32, m = 2^LM and
+// nz = 2^LZ at compile time): a work item holds one line per wavefront.  The
+// depth DFTs of its lines run together, then each wavefront spreads its line
+// into its own grid line in LDS (no block barrier inside), and the grid DFTs
+// of all lines run together; the last stage writes the picked, deconvolved
+// samples to memory.  LDS: the lines' grids (also the depth-FFT scratch) and
+// their depth spectra in natural order.
+template <int TAPS, int LM, int LZ>
+__global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
+  using T = float;
+  constexpr int m = 1 << LM, nz = 1 << LZ, NL = kBlock / 64;
+  using PM = P2Plan<LM>;
+  using PZ = P2Plan<LZ>;
+  static_assert(PM::nst >= 2 && PZ::nst >= 2 && LZ <= LM, "two or more stages");
+  cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // NL grid lines (first the depth-FFT scratch)
+  cx<T>* qn = grid + NL * m;                         // NL depth spectra, natural order
+  PAT_FOR_EACH_ITEM(a)
+  const int nt = I.nt;
+  const int line0 = li * NL;
+  const int nl = min(NL, I.lines - line0);
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[inst_]) + (size_t)line0 * nz;
+  constexpr int stepz = nz / PZ::rad(PZ::nst - 1);
+  fft_first_stage_p2<T, PZ::rad(0), true>(grid, nz, twz, nl, nz, 1,
+                                          [&](int b, int pos) { return in[(size_t)b * nz + pos]; });
+  __syncthreads();
+  p2_stages<T, LZ, 1>(grid, twz, nl);
+  fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(grid, nz, nl, nz, 1, [&](int b, int blk, const auto& v) {
+    constexpr int R = sizeof(v) / sizeof(v[0]);
+    cx<T>* d = qn + b * nz;
+    const int k0 = PZ::natural(blk * R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[k0 + r * stepz] = v[r];
+  });
+  __syncthreads();
+  const int wv = (int)(threadIdx.x >> 6);
+  if (wv < nl) {
+    const cx<T>* qb = qn + wv * nz;
+    spread_line_wave<TAPS, true>(I, a, line0 + wv, a.mode, m, nz, grid + wv * m, [&](int l) { return qb[l]; });
+  }
+  __syncthreads();
+  // X_n = s_n conj(G_k) for the natural index k = (n - nt/2) mod m
+  const T* sn = static_cast<const T*>(I.sn);
+  constexpr int step = m / PM::rad(PM::nst - 1);
+  cx<T>* xout = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt;
+  p2_stages<T, LM, 0>(grid, twm, nl);
+  fft_last_stage_p2<T, PM::rad(PM::nst - 1), true>(grid, m, nl, m, 1, [&](int b, int blk, const auto& v) {
+    constexpr int R = sizeof(v) / sizeof(v[0]);
+    const int k0 = PM::natural(blk * R);
+    cx<T>* x = xout + (size_t)b * nt;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int n = (k0 + r * step + nt / 2) & (m - 1);
+      if (n < nt) x[n] = cscl(cconj(v[r]), sn[n]);
+    }
+  });
+  PAT_END_ITEM
+}
+
+// Spreading alone with wavefront spreading (FP32 compute; grid stored as
+// float or bf16 pairs): one line per wavefront, built in LDS and written out
+// by the same wavefront with 16-byte stores.
+template <typename G, int TAPS, bool P2>
+__global__ __launch_bounds__(kBlock) void k_line_spread_w(StageArgs a) {
+  constexpr int NL = kBlock / 64;
+  PAT_FOR_EACH_ITEM(a)
+  const int m = I.m, nz = I.nz;
+  const int line0 = li * NL;
+  const int wv = (int)(threadIdx.x >> 6), L = (int)(threadIdx.x & 63);
+  if (line0 + wv < I.lines) {
+    const int line = line0 + wv;
+    cx<float>* Gl = reinterpret_cast<cx<float>*>(pat_smem) + wv * m;
+    const cx<float>* F = static_cast<const cx<float>*>(a.in[inst_]) + (size_t)line * nz;
+    spread_line_wave<TAPS, P2>(I, a, line, a.mode, m, nz, Gl, [&](int l) { return F[l]; });
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    G* row = static_cast<G*>(a.out[inst_]) + (size_t)line * m;
+    for (int j = 4 * L; j < m; j += 4 * 64) {
+      cx<float> v4[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v4[c] = cconj(Gl[j + c]);
+      grid_store4<float, G>(row + j, v4);
+    }
+  }
+  PAT_END_ITEM
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -2527,7 +2797,7 @@ hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t sh
   return e;
 }
 
-enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LA, IT_LINE };
+enum Items { IT_X1, IT_X2, IT_C2R, IT_LM, IT_LZ, IT_LI, IT_LF, IT_LA, IT_LINE, IT_LWAVE };
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -2543,6 +2813,7 @@ int items_of(const Inst& I, Items kind, bool nz) {
     case IT_LF: return cdiv(I.lines, I.lpw_f);
     case IT_LA: return cdiv(I.lines, I.lpw_a);
     case IT_LINE: return I.lines;
+    case IT_LWAVE: return cdiv(I.lines, kBlock / 64);  // one line per wavefront
   }
   return 0;
 }
@@ -2706,6 +2977,16 @@ struct Runner {
                   max_over([](const Inst& I) { return lds_interp(I, cs); }), st, tm);
   }
   hipError_t spread(const void* const* in, void* const* out, int mode) {
+    if constexpr (sizeof(T) == 4 && TAPS > 0 && TAPS % 2 == 0) {
+      // FP32 with the paired taps: one line per wavefront (its grid line in
+      // LDS, up to 2048 points)
+      StageArgs a = base(IT_LWAVE, true, mode, in, out);
+      const size_t shm = max_over([](const Inst& I) { return lds_spread_wave(I); });
+      bool ok = a.pair_ok && shm <= 65536;
+      for (int i = 0; i < n; ++i) ok = ok && h[i].m % 4 == 0;
+      if (ok) return launch(k_line_spread_w<G, TAPS, P2>, "spread", a, shm, st, tm);
+      next_counter--;  // (the counter taken by base() above is not used)
+    }
     StageArgs a = base(IT_LINE, true, mode, in, out);
     return launch(k_line_spread<T, G, TAPS>, "spread", a,
                   max_over([](const Inst& I) { return lds_spread(I, cs); }), st, tm);
@@ -2738,6 +3019,26 @@ struct Runner {
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
+    if constexpr (sizeof(T) == 4 && P2 && TAPS > 0 && TAPS % 2 == 0) {
+      // one line per wavefront, compile-time sizes for m = 2^8 .. 2^10 and
+      // nz = m/4 or m/2
+      const Inst& I = h[0];
+      const int lm = __builtin_ctz((unsigned)I.m), dz = lm - __builtin_ctz((unsigned)I.nz);
+      StageArgs a = base(IT_LWAVE, true, mode, in, out);
+      if (n == 1 && a.pair_ok && (dz == 1 || dz == 2) && lm >= 8 && lm <= 10) {
+        const size_t shm = lds_fused1_wave(I);
+        auto go = [&](auto kern) { return launch(kern, "nufft_adjoint_fused", a, shm, st, tm); };
+        if (dz == 2) {
+          if (lm == 8) return go(k_line_nufft1_w<TAPS, 8, 6>);
+          if (lm == 9) return go(k_line_nufft1_w<TAPS, 9, 7>);
+          return go(k_line_nufft1_w<TAPS, 10, 8>);
+        }
+        if (lm == 8) return go(k_line_nufft1_w<TAPS, 8, 7>);
+        if (lm == 9) return go(k_line_nufft1_w<TAPS, 9, 8>);
+        return go(k_line_nufft1_w<TAPS, 10, 9>);
+      }
+      next_counter--;
+    }
     StageArgs a = base(IT_LA, true, mode, in, out);
     if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
       // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2

@@ -114,6 +114,11 @@ inline size_t lds_fused2(const Inst& I, size_t cs) {
   const size_t sp = (size_t)(I.m > I.nz ? I.m : I.nz);
   return (size_t)I.lpw_f * (sp + (size_t)I.m) * cs;
 }
+// FP32 spreading by wavefronts: one grid line of m complex floats per
+// wavefront of the workgroup (stand-alone), plus the depth spectra in the
+// fused type-1 kernel
+inline size_t lds_spread_wave(const Inst& I) { return (size_t)(kBlock / 64) * I.m * 8; }
+inline size_t lds_fused1_wave(const Inst& I) { return (size_t)(kBlock / 64) * ((size_t)I.m + I.nz) * 8; }
 // fused type-1 line kernel: a region of max(m, lpw_a nz) (the depth FFTs,
 // then one grid line), lpw_a depth spectra in natural order, the lists
 inline size_t lds_fused1(const Inst& I, size_t cs) {
