@@ -1199,8 +1199,11 @@ __device__ __forceinline__ void seg_sum(const WaveSeg& s, float& x, float& y) {
 // One pass of a wavefront's nodes (monotone first taps j0 over the active
 // lanes, which come first): cell (j0 + t) mod m of the LDS line G gains
 // w[t] v for t < TAPS.  Inactive lanes carry v = 0 and keys of their own.
-// When the active first taps span m cells or more, two segments could share
-// a cell modulo m; the writes of each round then go one lane at a time.
+// When no writer's window runs past the end of the line, the cells are
+// addressed from one base per lane (the tap goes into the instruction's
+// offset).  When the active first taps span m cells or more, two segments
+// could share a cell modulo m; the writes of each round then go one lane at a
+// time.
 template <int TAPS, bool P2>
 __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bool act, int nact, cx<float> v,
                                                  const float* w) {
@@ -1216,43 +1219,102 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
     r += r < 0 ? m : 0;
   }
   const bool wr = act && sg.tail;
-#pragma unroll
-  for (int t = 0; t < TAPS; ++t) {
-    float x = w[t] * v.x, y = w[t] * v.y;
+  const bool flat = distinct && !__any(wr && r > m - TAPS);
+  cx<float>* g = G + r;
+  auto sum = [&](int t, float& x, float& y) {
+    x = w[t] * v.x;
+    y = w[t] * v.y;
     seg_sum(sg, x, y);
-    int c = r + t;
-    c -= c >= m ? m : 0;
-    if (distinct) {
+  };
+  if (flat) {
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      float x, y;
+      sum(t, x, y);
       if (wr) {
-        G[c].x += x;
-        G[c].y += y;
+        g[t].x += x;
+        g[t].y += y;
       }
-    } else {
-      for (int k = 0; k < 64; ++k) {
-        if (wr && L == k) {
+      // the next round's reads come after this round's writes
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      float x, y;
+      sum(t, x, y);
+      int c = r + t;
+      c -= c >= m ? m : 0;
+      if (distinct) {
+        if (wr) {
           G[c].x += x;
           G[c].y += y;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      } else {
+        for (int k = 0; k < 64; ++k) {
+          if (wr && L == k) {
+            G[c].x += x;
+            G[c].y += y;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
-    // the next round's reads come after this round's writes
+  }
+}
+
+// A few nodes (n <= 64 / TAPS, in lanes 0 .. n-1: first tap j0, value v,
+// weights w) spread tap-parallel: lane k TAPS + t adds tap t of node k, one
+// node per round.
+template <int TAPS, bool P2>
+__device__ __forceinline__ void spread_few_wave(cx<float>* G, int m, int n, int j0, cx<float> v, const float* w) {
+  const int L = (int)(threadIdx.x & 63);
+  const int k = L / TAPS, t = L - k * TAPS;
+  const int kk = k < n ? k : 0;
+  const int jk = __shfl(j0, kk, 64);
+  const float vx = __shfl(v.x, kk, 64), vy = __shfl(v.y, kk, 64);
+  float wt = 0.f;
+#pragma unroll
+  for (int i = 0; i < TAPS; ++i) {
+    const float wi = __shfl(w[i], kk, 64);
+    wt = t == i ? wi : wt;
+  }
+  int c;
+  if constexpr (P2) {
+    c = (jk + t) & (m - 1);
+  } else {
+    c = (jk + t) % m;
+    c += c < 0 ? m : 0;
+  }
+  for (int q = 0; q < n; ++q) {
+    if (k == q) {
+      G[c].x += wt * vx;
+      G[c].y += wt * vy;
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
 }
 
 // Spreading of one line by one wavefront into the LDS line G (m cells,
 // zeroed here), the same sums as spread_line: lane L of batch k takes
-// |l| = q0 + 64k + L and both its nodes -nu+ and +nu+ (one pass each).  The
-// grid receives the conjugated values, as spread_line's put does.
+// |l| = q0 + 64k + L and both its nodes +nu+ and -nu+ (one pass each).  The
+// two nodes' windows are mirror images: the tap weights of -nu+ are those of
+// +nu+ reversed and its first tap is -(j0 + TAPS - 1), except when c nu+ is
+// an integer (the node on a grid point), where both nodes' offsets are -1:
+// same weights, first tap -(j0 + TAPS - 2).  The grid receives the
+// conjugated values, as spread_line's put does.
 //   mode 0 (R^T): |l| = 1 .. nz/2, value conj(W exp(-i pi nu) scale) Qhat_l,
 //     l = sign(nu)|l|, the Nyquist pair both from Qhat_{-nz/2} at half weight;
 //   mode 1 (A): |l| = 0 .. nz/2, value (scale / 2) exp(i pi nu) (F_l + F_-l)
 //     (a single term at l = 0 and -nz/2).
-// fget(l_index) reads the line's depth spectrum (DFT order).
+// fget(l_index) reads the line's depth spectrum (DFT order).  A batch of at
+// most 64 / (2 TAPS) values of |l| (the last one of mode 1) spreads
+// tap-parallel.
 template <int TAPS, bool P2, typename Fget>
 __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs& a, int line, int mode, int m, int nz,
                                                  cx<float>* G, Fget fget) {
+  static_assert(TAPS % 2 == 0, "mirrored windows need an even tap count");
   const int L = (int)(threadIdx.x & 63);
   float4* G4 = reinterpret_cast<float4*>(G);
   for (int e = L; e < m / 2; e += 64) G4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1282,15 +1344,44 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       cf = 0.5 * I.scale;
     }
     const float cff = act ? (float)cf : 0.f;
-    const cx<float> vals[2] = {cscl(cmul(cconj(qp), ph), cff), cscl(cmul(cconj(qm), cconj(ph)), cff)};
+    const cx<float> vp = cscl(cmul(cconj(qp), ph), cff);
+    const cx<float> vm = cscl(cmul(cconj(qm), cconj(ph)), cff);
+    // +nu+: first tap j0, offset x, weights w; -nu+ mirrored (see above)
+    const double xc = I.c * nup;
+    const double f = floor(xc - I.ck);
+    const double d = xc - f - 1.0 - I.ck;  // (fractional part of c nu+) - 1
+    const float x = (float)(2.0 * d + 1.0);
+    const int j0 = (int)f + 1;
+    const bool ongrid = d == -1.0;
+    float w[TAPS], wm[TAPS];
+    tap_weights_pairs<float, TAPS>(a, x, w);
 #pragma unroll
-    for (int sgn = 0; sgn < 2; ++sgn) {
-      const double xc = I.c * (sgn ? -nup : nup);
-      const double f = floor(xc - I.ck);
-      const float x = (float)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
-      float w[TAPS];
-      tap_weights_pairs<float, TAPS>(a, x, w);
-      spread_pass_wave<TAPS, P2>(G, m, (int)f + 1, act, nact, vals[sgn], w);
+    for (int t = 0; t < TAPS; ++t) wm[t] = ongrid ? w[t] : w[TAPS - 1 - t];
+    const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
+    if (2 * nact * TAPS <= 64) {
+      // nodes +nu+ of lanes 0 .. nact-1, then -nu+ of the same lanes
+      const int n2 = 2 * nact;
+      const int src = L < nact ? L : L - nact;
+      const bool neg = L >= nact;
+      float ws[TAPS];
+#pragma unroll
+      for (int t = 0; t < TAPS; ++t) {
+        const float a0 = __shfl(w[t], src, 64), a1 = __shfl(wm[t], src, 64);
+        ws[t] = neg ? a1 : a0;
+      }
+      // (every shuffle runs on all lanes, then each lane selects: a shuffle
+      // inside one arm of a branch would read lanes the branch left inactive)
+      const int jsp = __shfl(j0, src, 64), jsm = __shfl(jm, src, 64);
+      const float vpx = __shfl(vp.x, src, 64), vpy = __shfl(vp.y, src, 64);
+      const float vmx = __shfl(vm.x, src, 64), vmy = __shfl(vm.y, src, 64);
+      const int js = neg ? jsm : jsp;
+      cx<float> vs;
+      vs.x = neg ? vmx : vpx;
+      vs.y = neg ? vmy : vpy;
+      spread_few_wave<TAPS, P2>(G, m, n2, js, vs, ws);
+    } else {
+      spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w);
+      spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm);
     }
   }
 }
@@ -2640,8 +2731,8 @@ template <int TAPS, int LM, int LZ>
 __global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
   using T = float;
   constexpr int m = 1 << LM, nz = 1 << LZ, NL = kBlock / 64;
-  using PM = P2Plan<LM>;
-  using PZ = P2Plan<LZ>;
+  using PM = P2Plan<LM, p2_l16_m(LM)>;  // (radix-16 last stages, as in the type-2 kernel)
+  using PZ = P2Plan<LZ, p2_l16_z(LZ)>;
   static_assert(PM::nst >= 2 && PZ::nst >= 2 && LZ <= LM, "two or more stages");
   cx<T>* grid = reinterpret_cast<cx<T>*>(pat_smem);  // NL grid lines (first the depth-FFT scratch)
   cx<T>* qn = grid + NL * m;                         // NL depth spectra, natural order
@@ -2656,7 +2747,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
   fft_first_stage_p2<T, PZ::rad(0), true>(grid, nz, twz, nl, nz, 1,
                                           [&](int b, int pos) { return in[(size_t)b * nz + pos]; });
   __syncthreads();
-  p2_stages<T, LZ, 1>(grid, twz, nl);
+  p2_stages<T, LZ, 1, p2_l16_z(LZ)>(grid, twz, nl);
   fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(grid, nz, nl, nz, 1, [&](int b, int blk, const auto& v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
     cx<T>* d = qn + b * nz;
@@ -2675,7 +2766,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
   const T* sn = static_cast<const T*>(I.sn);
   constexpr int step = m / PM::rad(PM::nst - 1);
   cx<T>* xout = static_cast<cx<T>*>(a.out[inst_]) + (size_t)line0 * nt;
-  p2_stages<T, LM, 0>(grid, twm, nl);
+  p2_stages<T, LM, 0, p2_l16_m(LM)>(grid, twm, nl);
   fft_last_stage_p2<T, PM::rad(PM::nst - 1), true>(grid, m, nl, m, 1, [&](int b, int blk, const auto& v) {
     constexpr int R = sizeof(v) / sizeof(v[0]);
     const int k0 = PM::natural(blk * R);
@@ -3188,6 +3279,10 @@ hipError_t spread_only(const Inst& h, const Inst* dinst, const void* hpoly, cons
   const void* in[1] = {vals};
   void* o[1] = {grid};
   if (h.taps == 12) {
+    if (h.pow2) {
+      Runner<T, G, 0, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
+      return r.spread(in, o, 0);
+    }
     Runner<T, G, 23, 12> r{1, &h, d, hp, nullptr, 0, st, tm};
     return r.spread(in, o, 0);
   }
