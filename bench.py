@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Vector FP32 (and FP64) rate without packed FP32 instructions, which the
+# build leaves out: 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz.
+PEAK_VALU_TFLOPS = 78.6
 WORKLOADS = {
     # name: (edge n, balls, seed)
     "planar-256x256x512-to-256^3": (256, 32, 1003),
@@ -54,6 +57,37 @@ def stage_bytes(name, n1, n2, nt, nz, m, prec):
         "idft_x1_c2r": lines * nz * cs + n1 * n2 * nz * rs,
         "nufft_fused": lines * nt * cs + lines * nz * cs,
     }.get(name)
+
+
+def stage_flops(name, n1, n2, nt, nz, m, taps=12):
+    """Algorithmic flops of one launch of the fused NUFFT stages, per line:
+    deconvolution (2 nt), the oversampled FFT (5 m log2 m), per node the tap
+    weights by the fitted even/odd polynomials (17 flops per tap pair plus
+    one square, the cheapest evaluation of the window transform this build
+    has), taps complex-by-real multiply-adds (4 each), phase and weight (8),
+    and the depth FFT (5 nz log2 nz).  None for other stages."""
+    if name not in ("nufft_fused", "nufft_adjoint_fused"):
+        return None
+    lines = (n1 // 2 + 1) * n2
+    per_node = 17 * (taps // 2) + 1 + 4 * taps + 8
+    per_line = 2 * nt + 5 * m * math.log2(m) + per_node * nz + 5 * nz * math.log2(nz)
+    return lines * per_line
+
+
+def roofline_of(name, nbytes, flops, ms):
+    """The bound of a kernel is the larger of its HBM time (algorithmic bytes
+    at 8 TB/s) and its vector-ALU time (algorithmic flops at the unpacked
+    FP32 rate); achieved and peak are stated in that bound's unit."""
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    t_alu = flops / (PEAK_VALU_TFLOPS * 1e12) if flops else 0.0
+    sec = ms * 1e-3
+    if t_alu > t_hbm:
+        ach = flops / sec / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_VALU_TFLOPS, "hbm_GBs": nbytes / sec / 1e9,
+                "hbm_frac": nbytes / sec / 1e9 / PEAK_HBM_GBS}
+    ach = nbytes / sec / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
 
 
 def kernel_source_hash():
@@ -124,7 +158,7 @@ def standalone_stages(n, g, steps, torch, dev, pat):
     return res
 
 
-def batched_and_small(steps, torch, dev, pat, inputs, np):
+def batched_and_small(steps, torch, dev, pat, inputs, np, keep=None):
     """The other throughput configurations: sixteen uneven instances (plane
     edges 64 .. 184, time samples twice the edge, depth the edge) in one
     persistent launch per stage, against one R call per instance; and the
@@ -155,6 +189,8 @@ def batched_and_small(steps, torch, dev, pat, inputs, np):
     t_s = (time.perf_counter() - t0) / steps * 1e3
     dev_rel = max(float((torch.linalg.vector_norm(o - s) / torch.linalg.vector_norm(s)).item())
                   for o, s in zip(outs, singles))
+    if keep is not None:
+        keep["batched"] = [(p_np, g, o.cpu().numpy()) for (p_np, g, _), o in zip(cases, outs)]
     out["batched_16_uneven"] = {
         "edges": [pl.n1 for pl in plans], "total_voxels": vox, "ms_per_launch_set": t_b,
         "voxels_per_s": vox / (t_b * 1e-3), "sequential_single_calls_ms": t_s,
@@ -168,6 +204,8 @@ def batched_and_small(steps, torch, dev, pat, inputs, np):
         plan.reconstruct(p, out=f)
     ms = time_steps(plan, p, f, steps, torch)
     out["planar-128x128x256-to-128^3"] = {"ms_per_step": ms, "voxels_per_s": 128 ** 3 / (ms * 1e-3)}
+    if keep is not None:
+        keep["planar128"] = (p_np, g, f.cpu().numpy())
     return out
 
 
@@ -306,6 +344,50 @@ def cpu_baseline(p_np, g, f_gpu, budget_s, np):
         "sample_relL2_gpu_vs_oracle": rel,
         "host_cpus": len(os.sched_getaffinity(0)),
     }
+
+
+def oracle_parity(p_np, g, outputs, keep, np):
+    """Part of the oracle leg: the GPU outputs against the oracle.
+    * each precision's R at full size on 64 sampled lines (and their mirrors),
+      by the oracle's direct sums there;
+    * every instance of the batched launch on 8 sampled lines;
+    * one full oracle reconstruction of the 128^2 x 256 -> 128^3 workload,
+      timed on the host cores, against the GPU's output in full."""
+    from oracle import recon
+
+    def sampled(f_gpu, p, gg, lines):
+        n1, n2, nz = gg["n1"], gg["n2"], gg["nz"]
+        ora = recon.spectrum_lines(p, gg, lines)
+        mir = recon.spectrum_lines(p, gg, [(-a, -b) for a, b in lines])
+        D = np.fft.fftn(f_gpu.astype(np.float64).reshape(n1, n2, nz))
+        lneg = (-np.arange(nz)) % nz
+        got = np.array([D[a % n1, b % n2, :] for a, b in lines])
+        exp = 0.5 * (ora + np.conj(mir[:, lneg]))
+        return float(np.linalg.norm(got - exp) / np.linalg.norm(exp))
+
+    res = {}
+    rng = np.random.default_rng(2024)
+    n1, n2 = g["n1"], g["n2"]
+    lines = [(int(rng.integers(-n1 // 2, n1 // 2)), int(rng.integers(-n2 // 2, n2 // 2))) for _ in range(64)]
+    res["sampled_lines_relL2_vs_oracle"] = {k: sampled(v, p_np, g, lines) for k, v in outputs.items()}
+    res["sampled_lines"] = len(lines)
+    if "batched" in keep:
+        per = []
+        for p, gg, out in keep["batched"]:
+            e = gg["n1"]
+            ls = [(e // 2, e // 2), (0, 1)] + [(int(rng.integers(-e // 2, e // 2)), int(rng.integers(-e // 2, e // 2)))
+                                               for _ in range(6)]
+            per.append({"edge": e, "relL2_vs_oracle_8_lines": sampled(out, p, gg, ls)})
+        res["batched_16_uneven_per_instance"] = per
+    if "planar128" in keep:
+        p, gg, f128 = keep["planar128"]
+        t0 = time.perf_counter()
+        ref = recon.reconstruct(p, gg)
+        t = time.perf_counter() - t0
+        res["full_oracle_planar-128x128x256-to-128^3"] = {
+            "seconds": t, "voxels_per_s": 128 ** 3 / t,
+            "gpu_f32_relL2_vs_oracle": float(np.linalg.norm(f128 - ref) / np.linalg.norm(ref))}
+    return res
 
 
 KERNEL_OF_STAGE = {
@@ -447,7 +529,8 @@ def main():
     dom = max(stages, key=stages.get)
     dom_ms = stages[dom]
     dom_bytes = stage_bytes(dom, n, n, nt, nz, m, args.precision)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    dom_flops = stage_flops(dom, n, n, nt, nz, m)
+    roof = roofline_of(dom, dom_bytes, dom_flops, dom_ms)
     nufft_ms = sum(stages.get(k, 0.0) for k in ("deconv_pad_fft", "interp", "nufft_fused"))
     f_host = f.cpu().numpy()
     phantom = inputs.ball_volume(balls, n, n, nz, g["dx"], g["dz"])
@@ -481,10 +564,9 @@ def main():
         "nufft_pts_per_s": vox / (nufft_ms * 1e-3) if nufft_ms > 0 else None,
         "stage_ms": stages,
         "relL2_vs_phantom": rel_phantom,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
-                     "launches_timed": counts[dom]},
+        "roofline": dict(roof, kernel=dom, traffic=traffic, algorithmic_bytes_per_launch=dom_bytes,
+                         algorithmic_flops_per_launch=dom_flops, avg_launch_ms=dom_ms,
+                         launches_timed=counts[dom]),
     }
     # adjoint R^T on the same plan (the gradient of R)
     q = f.detach().clone()
@@ -506,6 +588,12 @@ def main():
         acc.setdefault(name, []).append(ms_)
     plan.set_timing(False)
     out["adjoint_stage_ms"] = {k: sum(v) / len(v) for k, v in acc.items()}
+    if "nufft_adjoint_fused" in out["adjoint_stage_ms"]:
+        adj_ms = out["adjoint_stage_ms"]["nufft_adjoint_fused"]
+        out["adjoint_roofline"] = dict(
+            roofline_of("nufft_adjoint_fused", stage_bytes("nufft_fused", n, n, nt, nz, m, args.precision),
+                        stage_flops("nufft_adjoint_fused", n, n, nt, nz, m), adj_ms),
+            kernel="nufft_adjoint_fused", avg_launch_ms=adj_ms)
     del plan, f, q, pt
     # R with the smooth cut-off of the partial-data model (eps = 4 steps):
     # the weights are applied inside the first transverse pass
@@ -514,9 +602,21 @@ def main():
                                "dft_x1_ms_without": stages.get("dft_x1")}
     del planc, fc
     out["standalone"] = standalone_stages(n, g, args.steps, torch, dev, pat)
+    keep = {}
+    outputs = {args.precision: f_host}
+    if args.precision == "f32":
+        # the bf16-grid option on the same workload (staged kernels: the option
+        # concerns the stored grid)
+        print("[bench] timing bf16grid", file=sys.stderr, flush=True)
+        planb, fb, msb, stb, _ = run_prec("bf16grid")
+        fbh = fb.cpu().numpy()
+        outputs["bf16grid"] = fbh
+        out["bf16grid_path"] = {"ms_per_step": msb, "value": vox / (msb * 1e-3), "stage_ms": stb,
+                                "relL2_vs_f32": float(np.linalg.norm(fbh - f_host) / np.linalg.norm(f_host))}
+        del planb, fb
     if not args.no_extra:
         print("[bench] batched and 128^3 workloads", file=sys.stderr, flush=True)
-        out["other_workloads"] = batched_and_small(args.steps, torch, dev, pat, inputs, np)
+        out["other_workloads"] = batched_and_small(args.steps, torch, dev, pat, inputs, np, keep)
         print("[bench] interpolation methods", file=sys.stderr, flush=True)
         out["interpolation_study"] = interpolation_study(p_np, g, max(3, args.steps // 4), torch, dev, pat, np)
         print("[bench] circle experiment", file=sys.stderr, flush=True)
@@ -525,6 +625,7 @@ def main():
         print("[bench] timing f64", file=sys.stderr, flush=True)
         plan64, f64, ms64, st64, _ = run_prec("f64")
         f64h = f64.cpu().numpy()
+        outputs["f64"] = f64h
         out["fp64_path"] = {"ms_per_step": ms64, "value": vox / (ms64 * 1e-3), "stage_ms": st64,
                             "speedup_fp32_over_fp64": ms64 / ms,
                             "relL2_fp32_vs_fp64_gpu": float(np.linalg.norm(f_host - f64h) / np.linalg.norm(f64h)),
@@ -533,6 +634,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p_np, g, f_host, args.cpu_budget, np)
+        print("[bench] oracle parity", file=sys.stderr, flush=True)
+        out["oracle_parity"] = oracle_parity(p_np, g, outputs, keep, np)
     print(json.dumps(out), flush=True)
 
 

@@ -1171,7 +1171,7 @@ __device__ __forceinline__ WaveSeg wave_segments(int key) {
   unsigned u = 0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) u |= __ballot((f >> k) & 1u) ? (1u << k) : 0u;
-  s.use = u;
+  s.use = __builtin_amdgcn_readfirstlane(u);  // (uniform: keep it in a scalar register)
   return s;
 }
 
