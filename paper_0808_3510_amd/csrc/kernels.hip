@@ -1204,11 +1204,16 @@ __device__ __forceinline__ void seg_sum(const WaveSeg& s, float& x, float& y) {
 // offset).  When the active first taps span m cells or more, two segments
 // could share a cell modulo m; the writes of each round then go one lane at a
 // time.
+// The segments of a pass's keys: first taps, with keys of their own for the
+// inactive lanes.
+__device__ __forceinline__ WaveSeg pass_segments(int j0, bool act) {
+  return wave_segments(act ? j0 : (0x40000000 + (int)(threadIdx.x & 63)));
+}
+
 template <int TAPS, bool P2>
 __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bool act, int nact, cx<float> v,
-                                                 const float* w) {
+                                                 const float* w, const WaveSeg& sg) {
   const int L = (int)(threadIdx.x & 63);
-  const WaveSeg sg = wave_segments(act ? j0 : (0x40000000 + L));
   const int jf = __shfl(j0, 0, 64), jl = __shfl(j0, nact - 1, 64);
   const bool distinct = (jf > jl ? jf - jl : jl - jf) < m;
   int r;  // j0 mod m
@@ -1355,8 +1360,12 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
     const bool ongrid = d == -1.0;
     float w[TAPS], wm[TAPS];
     tap_weights_pairs<float, TAPS>(a, x, w);
+    // (a bitwise select: the conditional form became a select of array
+    // indices, which the compiler lowered to compare chains)
+    const unsigned keep = ongrid ? ~0u : 0u;
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) wm[t] = ongrid ? w[t] : w[TAPS - 1 - t];
+    for (int t = 0; t < TAPS; ++t)
+      wm[t] = __uint_as_float((__float_as_uint(w[t]) & keep) | (__float_as_uint(w[TAPS - 1 - t]) & ~keep));
     const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
     if (2 * nact * TAPS <= 64) {
       // nodes +nu+ of lanes 0 .. nact-1, then -nu+ of the same lanes
@@ -1380,8 +1389,16 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       vs.y = neg ? vmy : vpy;
       spread_few_wave<TAPS, P2>(G, m, n2, js, vs, ws);
     } else {
-      spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w);
-      spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm);
+      // equal first taps of +nu+ give equal first taps of -nu+ (and the
+      // reverse), so the two passes share their segments unless a node sits
+      // on a grid point
+      const WaveSeg sg = pass_segments(j0, act);
+      spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
+      if (__any(act && ongrid)) {
+        spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
+      } else {
+        spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, sg);
+      }
     }
   }
 }
