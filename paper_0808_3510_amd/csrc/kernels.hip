@@ -698,18 +698,19 @@ __device__ __forceinline__ T tap_poly(const T* __restrict__ c, T x) {
   return w;
 }
 
-// Node position on the oversampled grid: x = c nu, first tap j0 = floor(x - cK) + 1,
-// fractional offset delta = x - j0 in (cK - 1, cK].  Formed in double.
-struct NodePos {
-  int j0;
-  double delta;
-};
-__device__ __forceinline__ NodePos node_pos(double nu, double c, double ck) {
-  const double x = c * nu;
-  NodePos p;
-  p.j0 = (int)floor(x - ck) + 1;
-  p.delta = x - (double)p.j0;
-  return p;
+// First tap of a node at grid position xc = c nu: j0 = floor(xc - cK) + 1,
+// with d = xc - j0 - cK + 1 - 1 = (fractional part of xc) - 1 returned; the
+// node's tap offset is x = 2 d + 1 in [-1, 1).  Formed in double without
+// contraction (the subtractions see the rounded xc).  Where the paired taps
+// are used, the window of -nup is never formed from -xc but as the mirror
+// image of +nup's (interp_pair, spread_node, spread_line_wave): near 0,
+// rounding in xc - cK can make the direct form pick the window one end tap
+// over, and the interpolation and the spreading must agree on the window.
+__device__ __forceinline__ double tap_origin(double xc, double ck, int* j0) {
+#pragma clang fp contract(off)
+  const double f = floor(xc - ck);
+  *j0 = (int)f + 1;
+  return xc - f - 1.0 - ck;
 }
 
 // exp(-i pi nu), argument reduced in double to r in [-1, 1].  Double: the
@@ -821,15 +822,15 @@ struct Node {
 };
 template <typename T, bool P2>
 __device__ __forceinline__ Node<T> make_node(double nu, const Inst& I, int m, double inv_m) {
-  const double xc = I.c * nu;
-  const double f = floor(xc - I.ck);
+  int j00;
+  const double d = tap_origin(I.c * nu, I.ck, &j00);
   Node<T> nd;
-  nd.x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
+  nd.x = (T)(2.0 * d + 1.0);
   if constexpr (P2) {
-    nd.j0 = ((int)f + 1) & (m - 1);
+    nd.j0 = j00 & (m - 1);
   } else {
-    // (f + 1) mod m without an integer division
-    const double j1 = f + 1.0;
+    // j00 mod m without an integer division
+    const double j1 = (double)j00;
     int j0 = (int)(j1 - (double)m * floor(j1 * inv_m));
     if (j0 >= m) j0 -= m;
     if (j0 < 0) j0 += m;
@@ -881,15 +882,85 @@ __device__ __forceinline__ cx<T> tap_sum(const cx<T>* U, int m, double inv_m, do
   return acc;
 }
 
+// a when keep, else b, as a bitwise select (a conditional on array elements
+// may be lowered to a select of indices and compare chains)
+__device__ __forceinline__ float bitsel(bool keep, float a, float b) {
+  const unsigned k = keep ? ~0u : 0u;
+  return __uint_as_float((__float_as_uint(a) & k) | (__float_as_uint(b) & ~k));
+}
+__device__ __forceinline__ double bitsel(bool keep, double a, double b) {
+  const unsigned long long k = keep ? ~0ull : 0ull;
+  return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(a) & k) |
+                                          ((unsigned long long)__double_as_longlong(b) & ~k)));
+}
+
+// j mod m for a first tap j of either sign
+template <bool P2>
+__device__ __forceinline__ int wrap_tap(int j, int m, double inv_m) {
+  if constexpr (P2) {
+    return j & (m - 1);
+  } else {
+    const double jd = (double)j;
+    int r = (int)(jd - (double)m * floor(jd * inv_m));
+    if (r >= m) r -= m;
+    if (r < 0) r += m;
+    return r;
+  }
+}
+
+// sum_t w[t] U[(j + t) mod m], j in [0, m)
+template <typename T, int TAPS, bool HALO>
+__device__ __forceinline__ cx<T> taps_at(const cx<T>* U, int m, int j, const T* w) {
+  cx<T> acc = mk(T(0), T(0));
+  if (HALO || j <= m - TAPS) {
+    const cx<T>* u = U + j;
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      const cx<T> g = u[t];
+      acc.x += w[t] * g.x;
+      acc.y += w[t] * g.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      int jt = j + t;
+      jt -= jt >= m ? m : 0;
+      const cx<T> g = U[jt];
+      acc.x += w[t] * g.x;
+      acc.y += w[t] * g.y;
+    }
+  }
+  return acc;
+}
+
 // The type-2 values at the node pair +nup and -nup:
-// exp(-+i pi nup) sum_t phi(...) U[...]; the two phases are conjugate.
+// exp(-+i pi nup) sum_t phi(...) U[...]; the two phases are conjugate.  With
+// the paired taps the two windows are mirror images (the kernel is even and
+// cK = TAPS/2 is an integer): -nup's first tap is -(j0 + TAPS - 1) and its
+// weights are +nup's reversed, except for a node on a grid point (c nup an
+// integer), where both offsets are -1: the same weights, first tap
+// -(j0 + TAPS - 2).  So the window polynomials run once per pair.
 template <typename T, int TAPS, bool PAIRS, bool P2, bool HALO = true>
 __device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m, double nup, const Inst& I,
                                             const StageArgs& a, cx<T>* vp, cx<T>* vn) {
   // (an uncentred grid, the interpolation-based methods, needs no node phase)
   const cx<T> ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
-  *vp = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, nup, I, a), ph);
-  *vn = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, -nup, I, a), cconj(ph));
+  if constexpr (PAIRS) {
+    int j0;
+    const double d = tap_origin(I.c * nup, I.ck, &j0);
+    const T x = (T)(2.0 * d + 1.0);
+    const bool ongrid = d == -1.0;
+    T w[TAPS], wm[TAPS];
+    tap_weights_pairs<T, TAPS>(a, x, w);
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
+    const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
+    *vp = cmul(taps_at<T, TAPS, HALO>(U, m, wrap_tap<P2>(j0, m, inv_m), w), ph);
+    *vn = cmul(taps_at<T, TAPS, HALO>(U, m, wrap_tap<P2>(jm, m, inv_m), wm), cconj(ph));
+  } else {
+    *vp = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, nup, I, a), ph);
+    *vn = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, -nup, I, a), cconj(ph));
+  }
 }
 
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
@@ -985,25 +1056,35 @@ struct SpreadLds {
   }
 };
 
-// First tap and weight row of node i at nu.
+// First tap and weight row of node i at +nup (neg = false) or -nup.  With
+// the paired taps the window of -nup is the mirror image of +nup's, as in
+// interp_pair (so that spreading stays the exact transpose of interpolation):
+// first tap -(j0 + TAPS - 1) with the weights reversed, or -(j0 + TAPS - 2)
+// with the same weights for a node on a grid point.
 template <typename T, int TAPS, bool PAIRS, int KC>
-__device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, double nu, SpreadLds<T, KC> L, int i,
-                                            int taps, int rw) {
+__device__ __forceinline__ void spread_node(const Inst& I, const StageArgs& a, double nup, bool neg,
+                                            SpreadLds<T, KC> L, int i, int taps, int rw) {
   constexpr int P = SpreadLds<T, KC>::kPad;
-  const double xc = I.c * nu;
-  const double f = floor(xc - I.ck);
-  const T x = (T)(2.0 * (xc - f - 1.0 - I.ck) + 1.0);
-  L.j0s[i] = (int)f + 1;
   T* wi = L.wts + i * rw;
 #pragma unroll
   for (int t = 0; t < P; ++t) wi[t] = T(0);
   for (int t = P + taps; t < rw; ++t) wi[t] = T(0);
   if constexpr (PAIRS) {
+    int j0;
+    const double d = tap_origin(I.c * nup, I.ck, &j0);
+    const T x = (T)(2.0 * d + 1.0);
+    const bool ongrid = d == -1.0;
     T w[TAPS];
     tap_weights_pairs<T, TAPS>(a, x, w);
+    const bool rev = neg && !ongrid;
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) wi[P + t] = w[t];
+    for (int t = 0; t < TAPS; ++t) wi[P + t] = bitsel(rev, w[TAPS - 1 - t], w[t]);
+    L.j0s[i] = !neg ? j0 : (ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1));
   } else {
+    int j0;
+    const double d = tap_origin(I.c * (neg ? -nup : nup), I.ck, &j0);
+    const T x = (T)(2.0 * d + 1.0);
+    L.j0s[i] = j0;
     for (int t = 0; t < taps; ++t) wi[P + t] = tap_weight<T>(I, t, x);
   }
 }
@@ -1038,7 +1119,7 @@ __device__ __forceinline__ void spread_line(const Inst& I, const StageArgs& a, i
     // conjugate
     const cx<T> ph = phase_mpi<T>(nup);
     L.val[i] = cscl(cmul(q, pos ? cconj(ph) : ph), T(cf));
-    spread_node<T, TAPS, PAIRS, KC>(I, a, pos ? nup : -nup, L, i, taps, rw);
+    spread_node<T, TAPS, PAIRS, KC>(I, a, nup, !pos, L, i, taps, rw);
   }
   __syncthreads();
   const int jlo = L.j0s[0];
@@ -1352,20 +1433,14 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
     const cx<float> vp = cscl(cmul(cconj(qp), ph), cff);
     const cx<float> vm = cscl(cmul(cconj(qm), cconj(ph)), cff);
     // +nu+: first tap j0, offset x, weights w; -nu+ mirrored (see above)
-    const double xc = I.c * nup;
-    const double f = floor(xc - I.ck);
-    const double d = xc - f - 1.0 - I.ck;  // (fractional part of c nu+) - 1
+    int j0;
+    const double d = tap_origin(I.c * nup, I.ck, &j0);
     const float x = (float)(2.0 * d + 1.0);
-    const int j0 = (int)f + 1;
     const bool ongrid = d == -1.0;
     float w[TAPS], wm[TAPS];
     tap_weights_pairs<float, TAPS>(a, x, w);
-    // (a bitwise select: the conditional form became a select of array
-    // indices, which the compiler lowered to compare chains)
-    const unsigned keep = ongrid ? ~0u : 0u;
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t)
-      wm[t] = __uint_as_float((__float_as_uint(w[t]) & keep) | (__float_as_uint(w[TAPS - 1 - t]) & ~keep));
+    for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
     const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
     if (2 * nact * TAPS <= 64) {
       // nodes +nu+ of lanes 0 .. nact-1, then -nu+ of the same lanes
