@@ -32,6 +32,14 @@
  *    non-OK status.  No C++ exception crosses this boundary.
  *  - A plan may be used from one host thread at a time; different plans are
  *    independent.  Calls that share a workspace must be stream-ordered.
+ *  - Error injection: the environment variable PAT_FAULT, read at every call
+ *    that would touch the GPU, makes one HIP step report a failure before it
+ *    runs, so that the PAT_ERR_HIP path can be exercised: "upload" (the table
+ *    copy of pat_plan_upload), "scratch" (the scratch lookup of
+ *    pat_reconstruct_noalloc), "launch" or "launch:k" (the k-th kernel launch
+ *    of the operator, k >= 1; the kernels before it run, the output array is
+ *    written by the last kernel only and stays untouched).  Unset or empty:
+ *    no effect.
  */
 #ifndef PAT_H
 #define PAT_H

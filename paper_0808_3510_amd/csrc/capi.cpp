@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,6 +26,32 @@ pat_status hip_err(hipError_t e, const char* where) {
 }
 
 bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// The PAT_FAULT hook, read at the start of every call that touches the GPU:
+//   upload    pat_plan_upload's copy fails,
+//   scratch   pat_reconstruct_noalloc's scratch lookup fails,
+//   launch[:k] the k-th kernel launch of the operator fails (default 1),
+// each as a HIP error reported before that step runs.  Unset: no effect.
+struct Faults {
+  bool upload = false, scratch = false;
+};
+Faults arm_faults() {
+  Faults f;
+  int k = 0;
+  const char* v = std::getenv("PAT_FAULT");
+  if (v && *v) {
+    if (std::strcmp(v, "upload") == 0) {
+      f.upload = true;
+    } else if (std::strcmp(v, "scratch") == 0) {
+      f.scratch = true;
+    } else if (std::strncmp(v, "launch", 6) == 0) {
+      k = 1;
+      if (v[6] == ':') k = std::atoi(v + 7);
+    }
+  }
+  pat::set_launch_fault(k);
+  return f;
+}
 
 // hipEvent pairs around each kernel of a transform.
 class EventTimer : public pat::StageTimer {
@@ -108,6 +135,7 @@ pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, 
   pat_status s = check_call(plan, op, in, out);
   if (s != PAT_OK) return s;
   if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  arm_faults();
   return enqueue(plan, plan->inst, op, in, out, ws, stream, timer_of(plan));
 }
 
@@ -148,6 +176,8 @@ pat_status pat_plan_sizes(const pat_plan* plan, size_t* table_bytes, size_t* wor
 pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream) {
   if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
   if (!aligned16(table_dev)) return set_err(PAT_ERR_INVALID_ARG, "table buffer NULL or not 16-byte aligned");
+  const Faults f = arm_faults();
+  if (f.upload) return hip_err(hipErrorOutOfMemory, "hipMemcpyAsync(table) [PAT_FAULT=upload]");
   pat::bind_table(plan, table_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(table_dev, plan->blob.data(), plan->table_bytes, hipMemcpyHostToDevice, st);
@@ -190,6 +220,8 @@ pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, void* f, void*
     return set_err(PAT_ERR_UNSUPPORTED, "this plan needs " + std::to_string(need) +
                                             " bytes of workspace; the static scratch of pat_reconstruct_noalloc holds " +
                                             std::to_string(pat::kScratchBytes));
+  const Faults fl = arm_faults();
+  if (fl.scratch) return hip_err(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch) [PAT_FAULT=scratch]");
   void* ws = nullptr;
   hipError_t e = pat::scratch_buffer(&ws);
   if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)");
@@ -233,6 +265,7 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
     wsi[i] = w + off;
     off += align256(plans[i]->ws_bytes);
   }
+  arm_faults();
   hipError_t e = pat::run_op(plans[0]->prec, pat::OP_R, n, h, d, hp, p, f, wsi, counters,
                              static_cast<hipStream_t>(stream), timer_of(plans[0]));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -244,6 +277,7 @@ pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* s
   if (s != PAT_OK) return s;
   if (!aligned16(grid) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "grid/out NULL or not 16-byte aligned");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
+  arm_faults();
   hipError_t e = pat::run_interp(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, grid, out,
                                  static_cast<hipStream_t>(stream), timer_of(plan));
   if (e != hipSuccess) return hip_err(e, "kernel launch");
@@ -258,6 +292,7 @@ pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void
     return set_err(PAT_ERR_UNSUPPORTED, "spreading needs interp = PAT_INTERP_KB");
   if (!plan->spread_ok) return set_err(PAT_ERR_UNSUPPORTED, "nz too large for the spreading lists of a depth line in LDS");
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
+  arm_faults();
   hipError_t e = pat::run_spread(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, values, grid,
                                  static_cast<hipStream_t>(stream), timer_of(plan));
   if (e != hipSuccess) return hip_err(e, "kernel launch");

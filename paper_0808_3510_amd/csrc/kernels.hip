@@ -2937,9 +2937,16 @@ int resident_blocks(const void* kernel, size_t shmem) {
   return per_cu;
 }
 
+// launches left before an injected failure (0: none); see set_launch_fault
+thread_local int t_fault_countdown = 0;
+
+// True when this launch is the one the PAT_FAULT hook fails.
+bool launch_faulted() { return t_fault_countdown > 0 && --t_fault_countdown == 0; }
+
 template <typename K>
 hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st, StageTimer* tm) {
   if (a.total <= 0) return hipSuccess;
+  if (launch_faulted()) return hipErrorLaunchFailure;
   if (a.counter) {
     a.item_slot = (int32_t)((shmem + 15) & ~(size_t)15);
     shmem = (size_t)a.item_slot + 16;
@@ -2966,6 +2973,7 @@ template <typename K>
 hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st,
                              StageTimer* tm) {
   if (a.total <= 0) return hipSuccess;
+  if (launch_faulted()) return hipErrorLaunchFailure;
   if (shmem > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
@@ -3268,6 +3276,7 @@ hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const voi
     fused = fused && h[i].fused;
   }
   if (counters) {
+    if (launch_faulted()) return hipErrorLaunchFailure;
     if (tm) tm->begin("zero_counters", st);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters, kNumCounters);
     PAT_TRY(hipGetLastError());
@@ -3413,6 +3422,8 @@ hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void
 // host it is only a stand-in for the symbol): kernels get the device address
 // that hipGetSymbolAddress returns for the current device.
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void set_launch_fault(int k) { t_fault_countdown = k > 0 ? k : 0; }
 
 hipError_t scratch_buffer(void** ptr) {
   static std::mutex mu;

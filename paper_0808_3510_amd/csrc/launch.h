@@ -35,6 +35,11 @@ hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void
 hipError_t run_spread(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* vals,
                       void* grid, hipStream_t stream, StageTimer* timer);
 
+// Error injection (the PAT_FAULT hook of the C ABI): the k-th kernel launch
+// of the calling thread's next operator reports hipErrorLaunchFailure without
+// launching anything (k = 0: none).  Set at the start of every call.
+void set_launch_fault(int k);
+
 // Device address of the current device's kScratchBytes scratch array (a
 // file-scope __device__ array in kernels.hip), looked up with
 // hipGetSymbolAddress on the first call per device and cached.

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI, run by test_host_sanitized.py in a child
+process against the host-only library built with AddressSanitizer and
+UndefinedBehaviorSanitizer (build.build_host_sanitized): plan creation over
+valid and invalid geometries, sizes, status strings, batched sizing, the
+validation of every entry point before anything is enqueued, and the PAT_FAULT
+hook on the table upload.  Nothing here reaches a kernel launch or a HIP copy.
+
+Usage: python host_checks.py LIBRARY
+"""
+import ctypes
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_0808_3510_amd import pat  # noqa: E402
+
+pat.LIB_PATH = sys.argv[1]
+L = pat.lib()
+
+
+def geom(**kw):
+    base = dict(n1=16, n2=16, nt=32, nz=16, dx=1.0, dt=1.0, dz=1.0, vs=1.0, c=2.0, K=3.0, alpha=0.0,
+                precision="f32")
+    base.update(kw)
+    return pat.make_geometry(**base)
+
+
+def expect(status, fn, *args):
+    try:
+        fn(*args)
+    except pat.PatError as e:
+        assert e.status == status, (e.status, status, str(e))
+        assert pat.pat_last_error(), "empty error message"
+        return
+    assert status == 0, f"expected status {status}"
+
+
+valid = [dict(), dict(n2=1), dict(precision="f64"), dict(precision="bf16grid"), dict(n1=24, n2=20, nt=70, nz=18),
+         dict(c=4.0), dict(c=16.0, K=2.0, nt=64), dict(c=32.0, K=1.0, nt=16), dict(interp="linear", c=1.0),
+         dict(interp="nearest", c=2.0), dict(interp="sinc", c=2.0), dict(cutoff=2.5), dict(cutoff=4.0, n2=1, nt=64),
+         dict(n1=4096, n2=1, nt=8, nz=8), dict(nt=4096, nz=64, n1=2, n2=2), dict(nz=2048, nt=4096, n1=4, n2=1),
+         dict(n1=46, n2=38, nt=38, nz=34), dict(vs=1.7, dt=0.3, dz=0.9, dx=1.1)]
+invalid = [(dict(nt=31), 1), (dict(nz=0), 1), (dict(n1=15), 1), (dict(dx=0.0), 1), (dict(vs=float("inf")), 1),
+           (dict(c=1.0), 1), (dict(K=1.3), 1), (dict(alpha=3.0), 1), (dict(precision=9), 1), (dict(n1=58), 2),
+           (dict(nt=16384), 2), (dict(nt=8192, nz=64, n1=2, n2=2), 2), (dict(nz=8192, precision="f64"), 2), (dict(interp=9), 1), (dict(cutoff=-1.0), 1),
+           (dict(cutoff=4.5), 1), (dict(K=32.0), 1), (dict(c=2.0, K=3.0, nt=4), 1)]
+
+plans = []
+for kw in valid:
+    ptr = pat.pat_plan_create(geom(**kw))
+    tb, wb = pat.pat_plan_sizes(ptr)
+    assert tb > 0 and wb > 0, kw
+    plans.append(ptr)
+for kw, st in invalid:
+    expect(st, pat.pat_plan_create, geom(**kw))
+for s in range(7):
+    assert pat.pat_status_string(s)
+
+p0 = plans[0]
+# nothing runs before an upload, and no call accepts NULL or misaligned buffers
+expect(3, pat.pat_reconstruct, p0, 16, 16, 16, None)
+expect(3, pat.pat_reconstruct_noalloc, p0, 16, 16, None)
+expect(3, pat.pat_nufft2_lines, p0, 16, 16, None)
+expect(3, pat.pat_nufft1_lines, p0, 16, 16, None)
+assert L.pat_reconstruct(None, None, None, None, None) == 1
+assert L.pat_forward(None, None, None, None, None) == 1
+assert L.pat_plan_upload(p0, ctypes.c_void_p(8), None) == 1
+assert L.pat_plan_upload(None, ctypes.c_void_p(16), None) == 1
+assert L.pat_plan_sizes(None, None, None) == 1
+assert L.pat_plan_create(None, None) == 1
+assert L.pat_plan_set_fused(None, 1) == 1
+assert L.pat_plan_set_timing(None, 1) == 1
+n = ctypes.c_int32(-1)
+assert L.pat_plan_stage_times(p0, 4, None, None, ctypes.byref(n)) == 0 and n.value == 0
+# the bf16-grid plan has no fused kernels
+expect(2, pat.pat_plan_set_fused, plans[3], True)
+expect(0, pat.pat_plan_set_fused, plans[0], False)
+expect(0, pat.pat_plan_set_timing, plans[0], True)
+# batched sizing
+w = pat.pat_batched_workspace_size(plans[:4])
+assert w >= sum(pat.pat_plan_sizes(q)[1] for q in plans[:4])
+expect(1, pat.pat_batched_workspace_size, [])
+expect(1, pat.pat_batched_workspace_size, plans[:1] * 33)
+assert L.pat_reconstruct_batched(0, None, None, None, None, None) == 1
+# PAT_FAULT=upload: the table copy reports a HIP error before it runs; the
+# plan stays without tables
+os.environ["PAT_FAULT"] = "upload"
+expect(4, pat.pat_plan_upload, p0, 256, None)
+assert "PAT_FAULT" in pat.pat_last_error()
+os.environ["PAT_FAULT"] = ""
+expect(3, pat.pat_reconstruct, p0, 16, 16, 16, None)
+for q in plans:
+    pat.pat_plan_destroy(q)
+L.pat_plan_destroy(None)
+print("host checks passed")

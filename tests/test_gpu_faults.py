@@ -1,0 +1,99 @@
+"""The PAT_ERR_HIP path, forced from the host by the PAT_FAULT hook (a launch
+reports failure before it happens; every kernel that does run exits
+normally): each operator returns PAT_ERR_HIP whichever of its launches fails,
+its output array (written by the last kernel only) stays untouched, and the
+same calls succeed afterwards with the clean results."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_0808_3510_amd import inputs, pat
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture
+def fault_env():
+    old = os.environ.get("PAT_FAULT")
+    yield os.environ
+    if old is None:
+        os.environ.pop("PAT_FAULT", None)
+    else:
+        os.environ["PAT_FAULT"] = old
+
+
+def _plan(prec="f32", n=16):
+    return pat.Plan(n, n, 2 * n, n, 1 / n, 1 / n, 1 / n, precision=prec, device=DEV)
+
+
+@pytest.mark.parametrize("op,n_in,n_out,launches", [("reconstruct", 32, 16, 5), ("reconstruct_adjoint", 16, 32, 5),
+                                                   ("forward", 16, 32, 5), ("forward_adjoint", 32, 16, 5)])
+def test_injected_launch_failure(fault_env, op, n_in, n_out, launches):
+    print(f"fault injection {op}", flush=True)
+    plan = _plan()
+    x = torch.from_numpy(inputs.random_array((16, 16, n_in), 970)).to(DEV, torch.float32)
+    ref = getattr(plan, op)(x).clone()
+    for k in range(1, launches + 1):
+        fault_env["PAT_FAULT"] = f"launch:{k}"
+        out = torch.full((16, 16, n_out), 3.0, device=DEV)
+        with pytest.raises(pat.PatError) as ei:
+            getattr(plan, op)(x, out=out)
+        assert ei.value.status == 4 and "launch" in str(ei.value)
+        torch.cuda.synchronize()
+        assert torch.all(out == 3.0), k
+    # a launch past the last one: nothing fails
+    fault_env["PAT_FAULT"] = f"launch:{launches + 1}"
+    assert torch.equal(getattr(plan, op)(x), ref)
+    fault_env["PAT_FAULT"] = ""
+    assert torch.equal(getattr(plan, op)(x), ref)
+
+
+def test_injected_failures_batched_and_noalloc(fault_env):
+    print("fault injection batched / noalloc / line stages", flush=True)
+    plans = [_plan(n=16), _plan(n=24)]
+    ps = [torch.from_numpy(inputs.random_array((pl.n1, pl.n2, pl.nt), 971 + i)).to(DEV, torch.float32)
+          for i, pl in enumerate(plans)]
+    ref, ws = pat.reconstruct_batched(plans, ps)
+    ref = [r.clone() for r in ref]
+    for k in range(1, 7):  # the counter reset, then five stages
+        fault_env["PAT_FAULT"] = f"launch:{k}"
+        outs = [torch.full_like(r, 5.0) for r in ref]
+        with pytest.raises(pat.PatError) as ei:
+            pat.reconstruct_batched(plans, ps, outs, ws)
+        assert ei.value.status == 4
+        torch.cuda.synchronize()
+        assert all(torch.all(o == 5.0) for o in outs), k
+    plan = plans[0]
+    for mode in ("scratch", "launch:3"):
+        fault_env["PAT_FAULT"] = mode
+        out = torch.full_like(ref[0], 7.0)
+        with pytest.raises(pat.PatError) as ei:
+            plan.reconstruct_noalloc(ps[0], out=out)
+        assert ei.value.status == 4
+        torch.cuda.synchronize()
+        assert torch.all(out == 7.0)
+    vals = torch.ones((plan.lines, plan.nz), dtype=torch.complex64, device=DEV)
+    grid = torch.full((plan.lines, plan.m), 2.0 + 0j, dtype=torch.complex64, device=DEV)
+    fault_env["PAT_FAULT"] = "launch"
+    with pytest.raises(pat.PatError):
+        plan.nufft1_lines(vals, out=grid)
+    with pytest.raises(pat.PatError):
+        plan.nufft2_lines(grid, out=vals)
+    torch.cuda.synchronize()
+    assert torch.all(grid == 2.0) and torch.all(vals == 1.0)
+    fault_env["PAT_FAULT"] = ""
+    outs, _ = pat.reconstruct_batched(plans, ps, None, ws)
+    assert all(torch.equal(o, r) for o, r in zip(outs, ref))
+    assert torch.equal(plan.reconstruct_noalloc(ps[0]), ref[0])
+
+
+def test_injected_upload_failure(fault_env):
+    fault_env["PAT_FAULT"] = "upload"
+    with pytest.raises(pat.PatError) as ei:
+        _plan()
+    assert ei.value.status == 4
+    fault_env["PAT_FAULT"] = ""
+    assert _plan() is not None
