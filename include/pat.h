@@ -19,10 +19,15 @@
  *  - Element type: double for PAT_F64, float for PAT_F32 and
  *    PAT_F32_BF16GRID (the latter stores only the oversampled grid in bf16).
  *  - Every device pointer is caller-owned device memory on the device that is
- *    current when the call is made, 16-byte aligned.  The library allocates
- *    no device memory: the plan's constant tables live in a caller buffer of
- *    pat_plan_sizes().table_bytes filled by pat_plan_upload(), and every
- *    transform takes a caller workspace of pat_plan_sizes().workspace_bytes.
+ *    current when the call is made, 16-byte aligned, and comes with its size
+ *    in bytes.  The library allocates no device memory: the plan's constant
+ *    tables live in a caller buffer of pat_plan_sizes().table_bytes filled by
+ *    pat_plan_upload(), and every transform takes a caller workspace of
+ *    pat_plan_sizes().workspace_bytes.  A table or workspace smaller than that
+ *    gives PAT_ERR_WORKSPACE, an array smaller than its shape needs
+ *    PAT_ERR_INVALID_ARG.  Array sizes: data p  nx[0] nx[1] nt  elements,
+ *    image f  nx[0] nx[1] nz  elements (double for PAT_F64, else float);
+ *    line-stage arrays as described at pat_nufft2_lines.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
  *    work; results are ready when the stream is.
  *  - Errors: every argument is validated before anything is enqueued, so a
@@ -148,7 +153,7 @@ pat_status pat_plan_sizes(const pat_plan* plan, size_t* table_bytes, size_t* wor
 /* Copies the plan's tables into table_dev (table_bytes, caller-owned, must
  * stay alive while the plan is used) on `stream`, then synchronises the
  * stream.  Must precede any transform. */
-pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream);
+pat_status pat_plan_upload(pat_plan* plan, void* table_dev, size_t table_bytes, void* stream);
 
 /* R: reconstruction (Section 4, the NUFFT-based algorithm).  p -> f.
  *   a1  DFT over the detector axes (eq. fft-1a),
@@ -160,7 +165,8 @@ pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream);
  * The weight is 0 on the plane l = 0; on the depth-Nyquist plane l = -nz/2
  * the value is the mean of the two nodes +-|nu| (the real part of eq. fft-1).
  * p, f: device arrays as described above.  ws: workspace_bytes. */
-pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, void* stream);
+pat_status pat_reconstruct(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* R as pat_reconstruct, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -176,20 +182,24 @@ pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, voi
  * clearing: each call writes every part it reads).  Calls that overlap on one
  * device, on different streams or host threads, race on the array and must
  * be serialised by the caller.  Results equal pat_reconstruct's. */
-pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, void* f, void* stream);
+pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes,
+                                   void* stream);
 
 /* R^T: the exact transpose of R for the real inner product (type-1 NUFFT
  * spreading; the gradient of R).  f-shaped input -> p-shaped output. */
-pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, void* p, void* ws, void* stream);
+pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, size_t f_bytes, void* p, size_t p_bytes,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* A: the spectral forward model of the wave problem of Section 2 on the
  * periodic sampling grid, p[m, n] = Re( IDFT_x( (1/nz) sum_l F[k, l]
  * cos(2 pi |nu_{k,l}| n / nt) ) ), F the DFT of f over all axes; evaluated as
  * a type-1 NUFFT (spreading to the nodes +-|nu|).  f -> p. */
-pat_status pat_forward(pat_plan* plan, const void* f, void* p, void* ws, void* stream);
+pat_status pat_forward(pat_plan* plan, const void* f, size_t f_bytes, void* p, size_t p_bytes, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* A^T: transpose of A (type-2 interpolation at +-|nu|).  p -> f-shaped. */
-pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws, void* stream);
+pat_status pat_forward_adjoint(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* R for n independent plans (1 <= n <= 32) in one launch per stage: work
  * items (instance, tile or line) are drawn from a device work counter by a
@@ -197,7 +207,8 @@ pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws,
  * pat_reconstruct of plans[i]; ws of pat_batched_workspace_size() bytes. */
 pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes);
 pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p,
-                                   void* const* f, void* ws, void* stream);
+                                   const size_t* p_bytes, void* const* f, const size_t* f_bytes, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Stage a3 alone (type-2 interpolation + weight) on the half spectrum.
  * grid: (lines, c*nt) complex, lines = (nx[0]/2+1)*nx[1], line (k1, k2) at
@@ -209,7 +220,8 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
  * out: (lines, nz) complex in the plan's element type, l in DFT order:
  *   W_{k,l} T[G](nu_{k,l}) / (nx[0] nx[1] nz), with the l = 0 and l = -nz/2
  *   conventions of pat_reconstruct. */
-pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream);
+pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, size_t grid_bytes, void* out, size_t out_bytes,
+                            void* stream);
 
 /* Spreading alone (type-1; the step of R^T that pat_nufft2_lines mirrors):
  * the exact adjoint of pat_nufft2_lines for the complex inner product,
@@ -220,7 +232,8 @@ pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* s
  * half weight.  values: (lines, nz) complex in the plan's element type, l in
  * DFT order; grid: (lines, c*nt) in the plan's grid storage.  Deterministic
  * (no atomics). */
-pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void* stream);
+pat_status pat_nufft1_lines(pat_plan* plan, const void* values, size_t values_bytes, void* grid,
+                            size_t grid_bytes, void* stream);
 
 /* Line-stage layout.  By default (fused = 1) the deconvolution, oversampled
  * FFT, interpolation and depth DFT of each line group run in one kernel and

@@ -104,11 +104,28 @@ pat_status check_plan(const pat_plan* p) {
   return PAT_OK;
 }
 
+// Bytes of a plan's detector data (nt per column) or image (nz per column).
+size_t column_array_bytes(const pat_plan* p, bool image) {
+  const pat::Inst& I = p->inst;
+  return (size_t)I.n1 * I.n2 * (image ? I.nz : I.nt) * (pat::complex_bytes(p->prec) / 2);
+}
+
+pat_status check_size(const char* what, size_t have, size_t need, pat_status code) {
+  if (have >= need) return PAT_OK;
+  return set_err(code, std::string(what) + " holds " + std::to_string(have) + " bytes, the plan needs " +
+                           std::to_string(need));
+}
+
 // Checks shared by the single-plan operators (workspace aside).
-pat_status check_call(pat_plan* plan, pat::Op op, const void* in, void* out) {
+pat_status check_call(pat_plan* plan, pat::Op op, const void* in, size_t in_bytes, void* out, size_t out_bytes) {
   pat_status s = check_plan(plan);
   if (s != PAT_OK) return s;
   if (!aligned16(in) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
+  const bool in_image = op == pat::OP_RT || op == pat::OP_A;
+  s = check_size("input array", in_bytes, column_array_bytes(plan, in_image), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
+  s = check_size("output array", out_bytes, column_array_bytes(plan, !in_image), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
   if (op != pat::OP_R && plan->inst.kind != PAT_INTERP_KB)
     return set_err(PAT_ERR_UNSUPPORTED, "only the reconstruction runs with an interp other than PAT_INTERP_KB");
   if ((op == pat::OP_RT || op == pat::OP_A) && !plan->spread_ok)
@@ -131,10 +148,13 @@ pat_status enqueue(pat_plan* plan, const pat::Inst& h, pat::Op op, const void* i
   return PAT_OK;
 }
 
-pat_status run(pat_plan* plan, pat::Op op, const void* in, void* out, void* ws, void* stream) {
-  pat_status s = check_call(plan, op, in, out);
+pat_status run(pat_plan* plan, pat::Op op, const void* in, size_t in_bytes, void* out, size_t out_bytes, void* ws,
+               size_t ws_bytes, void* stream) {
+  pat_status s = check_call(plan, op, in, in_bytes, out, out_bytes);
   if (s != PAT_OK) return s;
   if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  s = check_size("workspace", ws_bytes, plan->ws_bytes, PAT_ERR_WORKSPACE);
+  if (s != PAT_OK) return s;
   arm_faults();
   return enqueue(plan, plan->inst, op, in, out, ws, stream, timer_of(plan));
 }
@@ -173,9 +193,11 @@ pat_status pat_plan_sizes(const pat_plan* plan, size_t* table_bytes, size_t* wor
   return PAT_OK;
 }
 
-pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream) {
+pat_status pat_plan_upload(pat_plan* plan, void* table_dev, size_t table_bytes, void* stream) {
   if (!plan) return set_err(PAT_ERR_INVALID_ARG, "plan is NULL");
   if (!aligned16(table_dev)) return set_err(PAT_ERR_INVALID_ARG, "table buffer NULL or not 16-byte aligned");
+  pat_status s = check_size("table buffer", table_bytes, plan->table_bytes, PAT_ERR_WORKSPACE);
+  if (s != PAT_OK) return s;
   const Faults f = arm_faults();
   if (f.upload) return hip_err(hipErrorOutOfMemory, "hipMemcpyAsync(table) [PAT_FAULT=upload]");
   pat::bind_table(plan, table_dev);
@@ -188,24 +210,29 @@ pat_status pat_plan_upload(pat_plan* plan, void* table_dev, void* stream) {
   return PAT_OK;
 }
 
-pat_status pat_reconstruct(pat_plan* plan, const void* p, void* f, void* ws, void* stream) {
-  return run(plan, pat::OP_R, p, f, ws, stream);
+pat_status pat_reconstruct(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes, void* ws,
+                           size_t ws_bytes, void* stream) {
+  return run(plan, pat::OP_R, p, p_bytes, f, f_bytes, ws, ws_bytes, stream);
 }
 
-pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, void* p, void* ws, void* stream) {
-  return run(plan, pat::OP_RT, f, p, ws, stream);
+pat_status pat_reconstruct_adjoint(pat_plan* plan, const void* f, size_t f_bytes, void* p, size_t p_bytes, void* ws,
+                           size_t ws_bytes, void* stream) {
+  return run(plan, pat::OP_RT, f, f_bytes, p, p_bytes, ws, ws_bytes, stream);
 }
 
-pat_status pat_forward(pat_plan* plan, const void* f, void* p, void* ws, void* stream) {
-  return run(plan, pat::OP_A, f, p, ws, stream);
+pat_status pat_forward(pat_plan* plan, const void* f, size_t f_bytes, void* p, size_t p_bytes, void* ws,
+                           size_t ws_bytes, void* stream) {
+  return run(plan, pat::OP_A, f, f_bytes, p, p_bytes, ws, ws_bytes, stream);
 }
 
-pat_status pat_forward_adjoint(pat_plan* plan, const void* p, void* f, void* ws, void* stream) {
-  return run(plan, pat::OP_AT, p, f, ws, stream);
+pat_status pat_forward_adjoint(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes, void* ws,
+                           size_t ws_bytes, void* stream) {
+  return run(plan, pat::OP_AT, p, p_bytes, f, f_bytes, ws, ws_bytes, stream);
 }
 
-pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, void* f, void* stream) {
-  pat_status s = check_call(plan, pat::OP_R, p, f);
+pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes,
+                                   void* stream) {
+  pat_status s = check_call(plan, pat::OP_R, p, p_bytes, f, f_bytes);
   if (s != PAT_OK) return s;
   // the fused line path never stores the oversampled grid: its workspace is
   // G and F only, packed back to back
@@ -241,11 +268,16 @@ pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t*
   return PAT_OK;
 }
 
-pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p, void* const* f, void* ws,
-                                   void* stream) {
-  if (!plans || !p || !f) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
+pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p, const size_t* p_bytes,
+                                   void* const* f, const size_t* f_bytes, void* ws, size_t ws_bytes, void* stream) {
+  if (!plans || !p || !f || !p_bytes || !f_bytes) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
   if (n < 1 || n > pat::kMaxBatch) return set_err(PAT_ERR_INVALID_ARG, "batch size must be in [1, 32]");
   if (!aligned16(ws)) return set_err(PAT_ERR_WORKSPACE, "workspace NULL or not 16-byte aligned");
+  size_t need = 0;
+  pat_status s0 = pat_batched_workspace_size(n, plans, &need);
+  if (s0 != PAT_OK) return s0;
+  s0 = check_size("workspace", ws_bytes, need, PAT_ERR_WORKSPACE);
+  if (s0 != PAT_OK) return s0;
   pat::Inst h[pat::kMaxBatch];
   const pat::Inst* d[pat::kMaxBatch];
   const void* hp[pat::kMaxBatch];
@@ -259,6 +291,10 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
     if (plans[i]->prec != plans[0]->prec) return set_err(PAT_ERR_INVALID_ARG, "plans in a batch must share a precision");
     if (!aligned16(p[i]) || !aligned16(f[i]))
       return set_err(PAT_ERR_INVALID_ARG, "input/output NULL or not 16-byte aligned");
+    s = check_size("input array", p_bytes[i], column_array_bytes(plans[i], false), PAT_ERR_INVALID_ARG);
+    if (s != PAT_OK) return s;
+    s = check_size("output array", f_bytes[i], column_array_bytes(plans[i], true), PAT_ERR_INVALID_ARG);
+    if (s != PAT_OK) return s;
     h[i] = plans[i]->inst;
     hp[i] = plans[i]->blob.data() + plans[i]->off_poly;
     d[i] = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plans[i]->table_dev) + plans[i]->off_desc);
@@ -272,10 +308,22 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
   return PAT_OK;
 }
 
-pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* stream) {
+// Bytes of the line-stage arrays: the oversampled grid (lines x c nt, grid
+// storage) and the node values (lines x nz complex).
+size_t grid_array_bytes(const pat_plan* p) { return (size_t)p->inst.lines * p->inst.m * pat::grid_bytes(p->prec); }
+size_t values_array_bytes(const pat_plan* p) {
+  return (size_t)p->inst.lines * p->inst.nz * pat::complex_bytes(p->prec);
+}
+
+pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, size_t grid_bytes, void* out, size_t out_bytes,
+                            void* stream) {
   pat_status s = check_plan(plan);
   if (s != PAT_OK) return s;
   if (!aligned16(grid) || !aligned16(out)) return set_err(PAT_ERR_INVALID_ARG, "grid/out NULL or not 16-byte aligned");
+  s = check_size("grid array", grid_bytes, grid_array_bytes(plan), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
+  s = check_size("output array", out_bytes, values_array_bytes(plan), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
   const pat::Inst* d = reinterpret_cast<const pat::Inst*>(static_cast<unsigned char*>(plan->table_dev) + plan->off_desc);
   arm_faults();
   hipError_t e = pat::run_interp(plan->prec, plan->inst, d, plan->blob.data() + plan->off_poly, grid, out,
@@ -284,10 +332,15 @@ pat_status pat_nufft2_lines(pat_plan* plan, const void* grid, void* out, void* s
   return PAT_OK;
 }
 
-pat_status pat_nufft1_lines(pat_plan* plan, const void* values, void* grid, void* stream) {
+pat_status pat_nufft1_lines(pat_plan* plan, const void* values, size_t values_bytes, void* grid, size_t grid_bytes,
+                            void* stream) {
   pat_status s = check_plan(plan);
   if (s != PAT_OK) return s;
   if (!aligned16(values) || !aligned16(grid)) return set_err(PAT_ERR_INVALID_ARG, "values/grid NULL or not 16-byte aligned");
+  s = check_size("values array", values_bytes, values_array_bytes(plan), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
+  s = check_size("grid array", grid_bytes, grid_array_bytes(plan), PAT_ERR_INVALID_ARG);
+  if (s != PAT_OK) return s;
   if (plan->inst.kind != PAT_INTERP_KB)
     return set_err(PAT_ERR_UNSUPPORTED, "spreading needs interp = PAT_INTERP_KB");
   if (!plan->spread_ok) return set_err(PAT_ERR_UNSUPPORTED, "nz too large for the spreading lists of a depth line in LDS");

@@ -50,20 +50,21 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0808_3510_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp = c_void_p
+        sz = c_size_t
         sig = {
             "pat_plan_create": (c_int32, [POINTER(pat_geometry), POINTER(c_void_p)]),
             "pat_plan_sizes": (c_int32, [vp, POINTER(c_size_t), POINTER(c_size_t)]),
-            "pat_plan_upload": (c_int32, [vp, vp, vp]),
-            "pat_reconstruct": (c_int32, [vp, vp, vp, vp, vp]),
-            "pat_reconstruct_noalloc": (c_int32, [vp, vp, vp, vp]),
-            "pat_reconstruct_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
-            "pat_forward": (c_int32, [vp, vp, vp, vp, vp]),
-            "pat_forward_adjoint": (c_int32, [vp, vp, vp, vp, vp]),
+            "pat_plan_upload": (c_int32, [vp, vp, sz, vp]),
+            "pat_reconstruct": (c_int32, [vp, vp, sz, vp, sz, vp, sz, vp]),
+            "pat_reconstruct_noalloc": (c_int32, [vp, vp, sz, vp, sz, vp]),
+            "pat_reconstruct_adjoint": (c_int32, [vp, vp, sz, vp, sz, vp, sz, vp]),
+            "pat_forward": (c_int32, [vp, vp, sz, vp, sz, vp, sz, vp]),
+            "pat_forward_adjoint": (c_int32, [vp, vp, sz, vp, sz, vp, sz, vp]),
             "pat_batched_workspace_size": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_size_t)]),
-            "pat_reconstruct_batched": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p),
-                                                  POINTER(c_void_p), vp, vp]),
-            "pat_nufft2_lines": (c_int32, [vp, vp, vp, vp]),
-            "pat_nufft1_lines": (c_int32, [vp, vp, vp, vp]),
+            "pat_reconstruct_batched": (c_int32, [c_int32, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_size_t),
+                                                  POINTER(c_void_p), POINTER(c_size_t), vp, sz, vp]),
+            "pat_nufft2_lines": (c_int32, [vp, vp, sz, vp, sz, vp]),
+            "pat_nufft1_lines": (c_int32, [vp, vp, sz, vp, sz, vp]),
             "pat_plan_set_fused": (c_int32, [vp, c_int32]),
             "pat_plan_set_timing": (c_int32, [vp, c_int32]),
             "pat_plan_stage_times": (c_int32, [vp, c_int32, POINTER(c_char_p), POINTER(c_float),
@@ -107,32 +108,36 @@ def pat_plan_sizes(plan: int) -> tuple[int, int]:
     return t.value, w.value
 
 
-def pat_plan_upload(plan: int, table: int, stream: int):
-    _check(lib().pat_plan_upload(plan, table, stream))
+def pat_plan_upload(plan: int, table: int, table_bytes: int, stream: int):
+    _check(lib().pat_plan_upload(plan, table, table_bytes, stream))
 
 
-def pat_reconstruct(plan, p, f, ws, stream):
-    _check(lib().pat_reconstruct(plan, p, f, ws, stream))
+def pat_reconstruct(plan, p, p_bytes, f, f_bytes, ws, ws_bytes, stream):
+    _check(lib().pat_reconstruct(plan, p, p_bytes, f, f_bytes, ws, ws_bytes, stream))
 
 
-def pat_reconstruct_noalloc(plan, p, f, stream):
-    _check(lib().pat_reconstruct_noalloc(plan, p, f, stream))
+def pat_reconstruct_noalloc(plan, p, p_bytes, f, f_bytes, stream):
+    _check(lib().pat_reconstruct_noalloc(plan, p, p_bytes, f, f_bytes, stream))
 
 
-def pat_reconstruct_adjoint(plan, f, p, ws, stream):
-    _check(lib().pat_reconstruct_adjoint(plan, f, p, ws, stream))
+def pat_reconstruct_adjoint(plan, f, f_bytes, p, p_bytes, ws, ws_bytes, stream):
+    _check(lib().pat_reconstruct_adjoint(plan, f, f_bytes, p, p_bytes, ws, ws_bytes, stream))
 
 
-def pat_forward(plan, f, p, ws, stream):
-    _check(lib().pat_forward(plan, f, p, ws, stream))
+def pat_forward(plan, f, f_bytes, p, p_bytes, ws, ws_bytes, stream):
+    _check(lib().pat_forward(plan, f, f_bytes, p, p_bytes, ws, ws_bytes, stream))
 
 
-def pat_forward_adjoint(plan, p, f, ws, stream):
-    _check(lib().pat_forward_adjoint(plan, p, f, ws, stream))
+def pat_forward_adjoint(plan, p, p_bytes, f, f_bytes, ws, ws_bytes, stream):
+    _check(lib().pat_forward_adjoint(plan, p, p_bytes, f, f_bytes, ws, ws_bytes, stream))
 
 
 def _ptr_array(vals):
     return (c_void_p * len(vals))(*vals)
+
+
+def _size_array(vals):
+    return (c_size_t * len(vals))(*vals)
 
 
 def pat_batched_workspace_size(plans) -> int:
@@ -141,17 +146,17 @@ def pat_batched_workspace_size(plans) -> int:
     return w.value
 
 
-def pat_reconstruct_batched(plans, ps, fs, ws, stream):
-    _check(lib().pat_reconstruct_batched(len(plans), _ptr_array(plans), _ptr_array(ps), _ptr_array(fs),
-                                         ws, stream))
+def pat_reconstruct_batched(plans, ps, p_bytes, fs, f_bytes, ws, ws_bytes, stream):
+    _check(lib().pat_reconstruct_batched(len(plans), _ptr_array(plans), _ptr_array(ps), _size_array(p_bytes),
+                                         _ptr_array(fs), _size_array(f_bytes), ws, ws_bytes, stream))
 
 
-def pat_nufft2_lines(plan, grid, out, stream):
-    _check(lib().pat_nufft2_lines(plan, grid, out, stream))
+def pat_nufft2_lines(plan, grid, grid_bytes, out, out_bytes, stream):
+    _check(lib().pat_nufft2_lines(plan, grid, grid_bytes, out, out_bytes, stream))
 
 
-def pat_nufft1_lines(plan, values, grid, stream):
-    _check(lib().pat_nufft1_lines(plan, values, grid, stream))
+def pat_nufft1_lines(plan, values, values_bytes, grid, grid_bytes, stream):
+    _check(lib().pat_nufft1_lines(plan, values, values_bytes, grid, grid_bytes, stream))
 
 
 def pat_plan_set_fused(plan, fused: bool):
@@ -201,6 +206,10 @@ def make_geometry(n1, n2, nt, nz, dx, dt, dz, vs=1.0, c=2.0, K=3.0, alpha=0.0, p
     return g
 
 
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
 def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -227,7 +236,7 @@ class Plan:
         self.ptr = pat_plan_create(self.geom)
         tb, wb = pat_plan_sizes(self.ptr)
         self.table = torch.empty(tb, dtype=torch.uint8, device=self.device)
-        pat_plan_upload(self.ptr, self.table.data_ptr(), _stream(self.device))
+        pat_plan_upload(self.ptr, self.table.data_ptr(), tb, _stream(self.device))
         self.ws = torch.empty(wb, dtype=torch.uint8, device=self.device)
 
     def __del__(self):
@@ -257,7 +266,8 @@ class Plan:
     def _call(self, fn, x, last_in, last_out, out=None):
         self._check(x, last_in, "input")
         y = self._out(x, last_out) if out is None else self._check(out, last_out, "output")
-        fn(self.ptr, x.data_ptr(), y.data_ptr(), self.ws.data_ptr(), _stream(self.device))
+        fn(self.ptr, x.data_ptr(), _nbytes(x), y.data_ptr(), _nbytes(y), self.ws.data_ptr(), _nbytes(self.ws),
+           _stream(self.device))
         return y
 
     # operators ------------------------------------------------------------
@@ -271,7 +281,7 @@ class Plan:
         caller's)."""
         self._check(p, self.nt, "input")
         y = self._out(p, self.nz) if out is None else self._check(out, self.nz, "output")
-        pat_reconstruct_noalloc(self.ptr, p.data_ptr(), y.data_ptr(), _stream(self.device))
+        pat_reconstruct_noalloc(self.ptr, p.data_ptr(), _nbytes(p), y.data_ptr(), _nbytes(y), _stream(self.device))
         return y
 
     def reconstruct_adjoint(self, q, out=None):
@@ -325,7 +335,7 @@ class Plan:
             out = torch.empty(vshape, dtype=vdt, device=self.device)
         else:
             self._check_lines(out, vshape, vdt, "out")
-        pat_nufft2_lines(self.ptr, grid.data_ptr(), out.data_ptr(), _stream(self.device))
+        pat_nufft2_lines(self.ptr, grid.data_ptr(), _nbytes(grid), out.data_ptr(), _nbytes(out), _stream(self.device))
         return out
 
     def nufft1_lines(self, values: torch.Tensor, out=None) -> torch.Tensor:
@@ -339,7 +349,8 @@ class Plan:
             out = torch.empty(gshape, dtype=gdt, device=self.device)
         else:
             self._check_lines(out, gshape, gdt, "out")
-        pat_nufft1_lines(self.ptr, values.data_ptr(), out.data_ptr(), _stream(self.device))
+        pat_nufft1_lines(self.ptr, values.data_ptr(), _nbytes(values), out.data_ptr(), _nbytes(out),
+                         _stream(self.device))
         return out
 
     def set_fused(self, fused: bool = True):
@@ -370,7 +381,8 @@ def reconstruct_batched(plans, ps, outs=None, ws=None):
     need = pat_batched_workspace_size(ptrs)
     if ws is None or ws.numel() < need or not plans[0]._on_device(ws) or not ws.is_contiguous():
         ws = torch.empty(need, dtype=torch.uint8, device=plans[0].device)
-    pat_reconstruct_batched(ptrs, [p.data_ptr() for p in ps], [o.data_ptr() for o in outs], ws.data_ptr(),
+    pat_reconstruct_batched(ptrs, [p.data_ptr() for p in ps], [_nbytes(p) for p in ps], [o.data_ptr() for o in outs],
+                            [_nbytes(o) for o in outs], ws.data_ptr(), _nbytes(ws),
                             _stream(plans[0].device))
     return outs, ws
 

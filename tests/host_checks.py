@@ -60,14 +60,15 @@ for s in range(7):
 
 p0 = plans[0]
 # nothing runs before an upload, and no call accepts NULL or misaligned buffers
-expect(3, pat.pat_reconstruct, p0, 16, 16, 16, None)
-expect(3, pat.pat_reconstruct_noalloc, p0, 16, 16, None)
-expect(3, pat.pat_nufft2_lines, p0, 16, 16, None)
-expect(3, pat.pat_nufft1_lines, p0, 16, 16, None)
-assert L.pat_reconstruct(None, None, None, None, None) == 1
-assert L.pat_forward(None, None, None, None, None) == 1
-assert L.pat_plan_upload(p0, ctypes.c_void_p(8), None) == 1
-assert L.pat_plan_upload(None, ctypes.c_void_p(16), None) == 1
+expect(3, pat.pat_reconstruct, p0, 16, 1 << 40, 16, 1 << 40, 16, 1 << 40, None)
+expect(3, pat.pat_reconstruct_noalloc, p0, 16, 1 << 40, 16, 1 << 40, None)
+expect(3, pat.pat_nufft2_lines, p0, 16, 1 << 40, 16, 1 << 40, None)
+expect(3, pat.pat_nufft1_lines, p0, 16, 1 << 40, 16, 1 << 40, None)
+assert L.pat_reconstruct(None, None, 0, None, 0, None, 0, None) == 1
+assert L.pat_forward(None, None, 0, None, 0, None, 0, None) == 1
+assert L.pat_plan_upload(p0, ctypes.c_void_p(8), 1 << 30, None) == 1
+assert L.pat_plan_upload(p0, ctypes.c_void_p(256), pat.pat_plan_sizes(p0)[0] - 1, None) == 3
+assert L.pat_plan_upload(None, ctypes.c_void_p(16), 1 << 30, None) == 1
 assert L.pat_plan_sizes(None, None, None) == 1
 assert L.pat_plan_create(None, None) == 1
 assert L.pat_plan_set_fused(None, 1) == 1
@@ -83,14 +84,14 @@ w = pat.pat_batched_workspace_size(plans[:4])
 assert w >= sum(pat.pat_plan_sizes(q)[1] for q in plans[:4])
 expect(1, pat.pat_batched_workspace_size, [])
 expect(1, pat.pat_batched_workspace_size, plans[:1] * 33)
-assert L.pat_reconstruct_batched(0, None, None, None, None, None) == 1
+assert L.pat_reconstruct_batched(0, None, None, None, None, None, None, 0, None) == 1
 # PAT_FAULT=upload: the table copy reports a HIP error before it runs; the
 # plan stays without tables
 os.environ["PAT_FAULT"] = "upload"
-expect(4, pat.pat_plan_upload, p0, 256, None)
+expect(4, pat.pat_plan_upload, p0, 256, pat.pat_plan_sizes(p0)[0], None)
 assert "PAT_FAULT" in pat.pat_last_error()
 os.environ["PAT_FAULT"] = ""
-expect(3, pat.pat_reconstruct, p0, 16, 16, 16, None)
+expect(3, pat.pat_reconstruct, p0, 16, 1 << 40, 16, 1 << 40, 16, 1 << 40, None)
 for q in plans:
     pat.pat_plan_destroy(q)
 L.pat_plan_destroy(None)

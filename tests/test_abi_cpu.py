@@ -72,14 +72,16 @@ def test_calls_before_upload_and_null_pointers_fail_cleanly():
     ptr = pat.pat_plan_create(_geom())
     try:
         with pytest.raises(pat.PatError) as ei:
-            pat.pat_reconstruct(ptr, 16, 16, 16, None)
+            pat.pat_reconstruct(ptr, 16, 1 << 40, 16, 1 << 40, 16, 1 << 40, None)
         assert ei.value.status == 3  # tables not uploaded
         L = pat.lib()
-        assert L.pat_reconstruct(None, None, None, None, None) == 1
+        assert L.pat_reconstruct(None, None, 0, None, 0, None, 0, None) == 1
         assert L.pat_plan_sizes(None, None, None) == 1
         assert L.pat_plan_create(None, None) == 1
         assert pat.pat_status_string(2) == "PAT_ERR_UNSUPPORTED"
-        assert L.pat_plan_upload(ptr, ctypes.c_void_p(8), None) == 1  # misaligned
+        assert L.pat_plan_upload(ptr, ctypes.c_void_p(8), 1 << 30, None) == 1  # misaligned
+        tb = pat.pat_plan_sizes(ptr)[0]
+        assert L.pat_plan_upload(ptr, ctypes.c_void_p(256), tb - 1, None) == 3  # short table buffer
     finally:
         pat.pat_plan_destroy(ptr)
 

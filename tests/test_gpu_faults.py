@@ -97,3 +97,43 @@ def test_injected_upload_failure(fault_env):
     assert ei.value.status == 4
     fault_env["PAT_FAULT"] = ""
     assert _plan() is not None
+
+
+def test_undersized_buffers_are_refused():
+    """Every buffer comes with its size: a short array gives
+    PAT_ERR_INVALID_ARG, a short workspace PAT_ERR_WORKSPACE, before anything
+    is enqueued (the output keeps its contents)."""
+    plan = _plan()
+    st = torch.cuda.current_stream().cuda_stream
+    P = torch.zeros((16, 16, 32), device=DEV)
+    F = torch.full((16, 16, 16), 9.0, device=DEV)
+    pb, fb, wb = P.numel() * 4, F.numel() * 4, plan.ws.numel()
+    cases = [((pb - 4, fb, wb), 1), ((pb, fb - 4, wb), 1), ((pb, fb, wb - 1), 3)]
+    for (a, b, c), code in cases:
+        with pytest.raises(pat.PatError) as ei:
+            pat.pat_reconstruct(plan.ptr, P.data_ptr(), a, F.data_ptr(), b, plan.ws.data_ptr(), c, st)
+        assert ei.value.status == code and "bytes" in str(ei.value)
+        with pytest.raises(pat.PatError) as ei:
+            pat.pat_reconstruct_adjoint(plan.ptr, F.data_ptr(), b, P.data_ptr(), a, plan.ws.data_ptr(), c, st)
+        assert ei.value.status == code
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_reconstruct_noalloc(plan.ptr, P.data_ptr(), pb, F.data_ptr(), fb - 4, st)
+    assert ei.value.status == 1
+    need = pat.pat_batched_workspace_size([plan.ptr])
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_reconstruct_batched([plan.ptr], [P.data_ptr()], [pb], [F.data_ptr()], [fb], ws.data_ptr(), need - 1, st)
+    assert ei.value.status == 3
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_reconstruct_batched([plan.ptr], [P.data_ptr()], [pb - 4], [F.data_ptr()], [fb], ws.data_ptr(), need, st)
+    assert ei.value.status == 1
+    grid = torch.zeros((plan.lines, plan.m), dtype=torch.complex64, device=DEV)
+    vals = torch.zeros((plan.lines, plan.nz), dtype=torch.complex64, device=DEV)
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_nufft2_lines(plan.ptr, grid.data_ptr(), grid.numel() * 8 - 8, vals.data_ptr(), vals.numel() * 8, st)
+    assert ei.value.status == 1
+    with pytest.raises(pat.PatError) as ei:
+        pat.pat_nufft1_lines(plan.ptr, vals.data_ptr(), vals.numel() * 8, grid.data_ptr(), grid.numel() * 8 - 8, st)
+    assert ei.value.status == 1
+    torch.cuda.synchronize()
+    assert torch.all(F == 9.0)

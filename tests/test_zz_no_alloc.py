@@ -39,7 +39,8 @@ def test_noalloc_two_calls_in_a_row_match_reconstruct():
     torch.cuda.synchronize()
     for g, plan, p, P, ref, out in cases:
         print(f"noalloc call {g}", flush=True)
-        pat.pat_reconstruct_noalloc(plan.ptr, P.data_ptr(), out.data_ptr(), stream())
+        pat.pat_reconstruct_noalloc(plan.ptr, P.data_ptr(), P.numel() * 4, out.data_ptr(), out.numel() * 4,
+                                    stream())
     torch.cuda.synchronize()
     for g, plan, p, P, ref, out in cases:
         assert torch.equal(out, ref), g
@@ -71,7 +72,8 @@ def test_noalloc_refuses_plans_beyond_the_scratch():
     P = torch.zeros((256, 256, 512), device=DEV)
     out = torch.full((256, 256, 256), 7.0, device=DEV)
     with pytest.raises(pat.PatError) as ei:
-        pat.pat_reconstruct_noalloc(plan.ptr, P.data_ptr(), out.data_ptr(), stream())
+        pat.pat_reconstruct_noalloc(plan.ptr, P.data_ptr(), P.numel() * 4, out.data_ptr(), out.numel() * 4,
+                                    stream())
     assert ei.value.status == 2 and "scratch" in str(ei.value)
     torch.cuda.synchronize()
     assert torch.all(out == 7.0)
