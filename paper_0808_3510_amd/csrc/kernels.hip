@@ -188,22 +188,64 @@ __device__ __forceinline__ void dft_pow2(cx<T>* v) {
   }
 }
 
-// Odd-prime butterfly: the R inputs are held in registers, outputs are formed
-// one at a time (roots exp(-2 pi i q / R) read from the L-point table at a
-// workgroup-uniform index) and written back, so no indexed local array is
-// needed.
+// The roots exp(-2 pi i q / R) of an odd prime R as compile-time constants:
+// cos and sin of 2 pi q / R from Taylor series in double on the angle
+// reduced to [-pi/4, pi/4] by quarter turns (error below 1e-16).
+struct RootTable {
+  double c[24], s[24];
+};
+constexpr RootTable make_roots(int R) {
+  RootTable t{};
+  for (int q = 0; q < R; ++q) {
+    const int k = (8 * q + R) / (2 * R);  // nearest multiple of a quarter turn
+    const double x = 3.14159265358979323846 * (double)(4 * q - k * R) / (2.0 * R);
+    double sn = x, cs = 1.0, ts = x, tc = 1.0;
+    for (int i = 1; i < 14; ++i) {
+      ts *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+      tc *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+      sn += ts;
+      cs += tc;
+    }
+    switch (k & 3) {
+      case 0: t.c[q] = cs; t.s[q] = sn; break;
+      case 1: t.c[q] = -sn; t.s[q] = cs; break;
+      case 2: t.c[q] = -cs; t.s[q] = -sn; break;
+      default: t.c[q] = sn; t.s[q] = -cs; break;
+    }
+  }
+  return t;
+}
+template <int R>
+struct Roots {
+  static constexpr RootTable t = make_roots(R);
+};
+// the same tables in constant memory, for the larger primes' rolled loops
+__constant__ RootTable kRoots11 = make_roots(11);
+__constant__ RootTable kRoots13 = make_roots(13);
+__constant__ RootTable kRoots17 = make_roots(17);
+__constant__ RootTable kRoots19 = make_roots(19);
+__constant__ RootTable kRoots23 = make_roots(23);
+template <int R>
+__device__ __forceinline__ const RootTable& root_table() {
+  if constexpr (R == 11) return kRoots11;
+  else if constexpr (R == 13) return kRoots13;
+  else if constexpr (R == 17) return kRoots17;
+  else if constexpr (R == 19) return kRoots19;
+  else return kRoots23;
+}
+
+// Odd-prime butterfly, all in registers: outputs d and R - d together, with
+// a_r = x_r + x_{R-r}, b_r = x_r - x_{R-r} (r = 1 .. H) and theta = 2 pi r d / R,
+//   X_d = x_0 + sum_r a_r cos(theta) - i sum_r b_r sin(theta),
+//   X_{R-d} = x_0 + sum_r a_r cos(theta) + i sum_r b_r sin(theta),
+// a quarter of the direct DFT's multiply-adds.  Up to R = 7 the cosines and
+// sines are compile-time constants (both loops unroll, so every index is
+// known); only the twiddles of the stage, exp(-2 pi i j d / Li), come from
+// the table.
 template <typename T, int R, typename Ptr>
-__device__ __forceinline__ void bfly_prime(Ptr p, int st, int j, int tws, const cx<T>* __restrict__ tw,
-                                           int L) {
-  // Odd prime R, outputs d and R - d together: with a_r = x_r + x_{R-r},
-  // b_r = x_r - x_{R-r} (r = 1 .. H) and theta = 2 pi r d / R,
-  //   X_d = x_0 + sum_r a_r cos(theta) - i sum_r b_r sin(theta),
-  //   X_{R-d} = x_0 + sum_r a_r cos(theta) + i sum_r b_r sin(theta).
-  // The roots exp(-2 pi i q / R) come from the length's table: held in
-  // registers for R <= 7, read per use for the larger primes (a loop over d
-  // that is not unrolled keeps their register footprint small).
+__device__ __forceinline__ void bfly_prime(Ptr p, int st, int j, int tws, const cx<T>* __restrict__ tw, int L) {
   constexpr int H = (R - 1) / 2;
-  const int step = L / R;
+  (void)L;
   const cx<T> x0 = ldx(p);
   cx<T> av[H + 1], bv[H + 1];
   cx<T> X0 = x0;
@@ -225,29 +267,25 @@ __device__ __forceinline__ void bfly_prime(Ptr p, int st, int j, int tws, const 
     stx(p + (R - d) * st, Xm);
   };
   if constexpr (R <= 7) {
-    T cq[H + 1], sq[H + 1];
-#pragma unroll
-    for (int q = 1; q <= H; ++q) {
-      const cx<T> w = tw[q * step];
-      cq[q] = w.x;
-      sq[q] = -w.y;
-    }
 #pragma unroll
     for (int d = 1; d <= H; ++d) {
       cx<T> A = x0, B = mk(T(0), T(0));
 #pragma unroll
       for (int r = 1; r <= H; ++r) {
-        const int q = (r * d) % R;  // compile-time
-        const T c = q <= H ? cq[q] : cq[R - q];
-        const T s = q <= H ? sq[q] : -sq[R - q];
+        const int q = (r * d) % R;
+        const T c = T(Roots<R>::t.c[q]), sn = T(Roots<R>::t.s[q]);
         A.x += av[r].x * c;
         A.y += av[r].y * c;
-        B.x += bv[r].x * s;
-        B.y += bv[r].y * s;
+        B.x += bv[r].x * sn;
+        B.y += bv[r].y * sn;
       }
       emit(d, A, B);
     }
   } else {
+    // the larger primes: one output pair at a time (a rolled loop keeps the
+    // register footprint of a fully unrolled butterfly out of the kernel),
+    // the roots read at a wave-uniform index from constant memory
+    const RootTable& rt = root_table<R>();
 #pragma unroll 1
     for (int d = 1; d <= H; ++d) {
       cx<T> A = x0, B = mk(T(0), T(0));
@@ -255,12 +293,12 @@ __device__ __forceinline__ void bfly_prime(Ptr p, int st, int j, int tws, const 
 #pragma unroll
       for (int r = 1; r <= H; ++r) {
         q += d;
-        if (q >= R) q -= R;
-        const cx<T> w = tw[q * step];  // (cos, -sin) of 2 pi q / R
-        A.x += av[r].x * w.x;
-        A.y += av[r].y * w.x;
-        B.x -= bv[r].x * w.y;
-        B.y -= bv[r].y * w.y;
+        q -= q >= R ? R : 0;
+        const T c = T(rt.c[q]), sn = T(rt.s[q]);
+        A.x += av[r].x * c;
+        A.y += av[r].y * c;
+        B.x += bv[r].x * sn;
+        B.y += bv[r].y * sn;
       }
       emit(d, A, B);
     }
@@ -313,6 +351,9 @@ __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* _
     lnbf = __builtin_ctz((unsigned)nbf);
     lnb = __builtin_ctz((unsigned)nb);
   }
+  // (one large-prime butterfly at a time: each has ILP of its own, and two
+  // in flight would double its register footprint)
+#pragma unroll(R >= 11 ? 1 : 0)
   for (int id = threadIdx.x; id < total; id += kBlock) {
     int b, bf;
     if constexpr (BF) {
@@ -3261,9 +3302,13 @@ struct Runner {
   } while (0)
 
 template <typename T, typename G, int RS, int TAPS>
-hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
-                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  Runner<T, G, RS, TAPS> r{n, h, d, hp, counters, 0, st, tm};
+hipError_t run_op_t(Op op, int stage, int n, const Inst* h, const Inst* const* d, const void* const* hp,
+                    const void* const* in, void* const* out, void* const* ws, uint32_t* counters, int counter0,
+                    hipStream_t st, StageTimer* tm) {
+  // stage s (1 .. 5) of the operator; the persistent launches of a stage
+  // take work counters from counter0 on (stage 3 may launch three kernels)
+  static const int kCounterAt[6] = {0, 0, 1, 2, 5, 6};
+  Runner<T, G, RS, TAPS> r{n, h, d, hp, counters, counter0 + kCounterAt[stage], st, tm};
   void* bg[kMaxBatch];
   void* bu[kMaxBatch];
   void* bf[kMaxBatch];
@@ -3275,42 +3320,26 @@ hipError_t run_op_t(Op op, int n, const Inst* h, const Inst* const* d, const voi
     bf[i] = w + h[i].off_f;
     fused = fused && h[i].fused;
   }
-  if (counters) {
-    if (launch_faulted()) return hipErrorLaunchFailure;
-    if (tm) tm->begin("zero_counters", st);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters, kNumCounters);
-    PAT_TRY(hipGetLastError());
-    if (tm) tm->end(st);
-  }
-  switch (op) {
-    case OP_R:
-    case OP_AT:
-      PAT_TRY(r.x1(in, bg, false));
-      PAT_TRY(r.x2(bg, false, 0));
-      if (fused) {
-        PAT_TRY(r.nufft2(bg, bf, op == OP_R ? 0 : 1));
-      } else {
+  const bool fwd = op == OP_R || op == OP_AT;  // type-2 line stage (else type-1)
+  void* const* a = fwd ? bg : bf;               // the transverse spectrum of the input
+  void* const* b = fwd ? bf : bg;               // the transverse spectrum of the output
+  const int mode = (op == OP_R || op == OP_RT) ? 0 : 1;
+  switch (stage) {
+    case 1: return r.x1(in, a, !fwd);
+    case 2: return r.x2(a, !fwd, 0);
+    case 3:
+      if (fwd) {
+        if (fused) return r.nufft2(bg, bf, mode);
         PAT_TRY(r.a2(bg, bu));
-        PAT_TRY(r.interp(bu, bf, op == OP_R ? 0 : 1));
-        PAT_TRY(r.zfft(bf, 1));
+        PAT_TRY(r.interp(bu, bf, mode));
+        return r.zfft(bf, 1);
       }
-      PAT_TRY(r.x2(bf, true, 1));
-      PAT_TRY(r.c2r(bf, out, true));
-      break;
-    case OP_RT:
-    case OP_A:
-      PAT_TRY(r.x1(in, bf, true));
-      PAT_TRY(r.x2(bf, true, 0));
-      if (fused) {
-        PAT_TRY(r.nufft1(bf, bg, op == OP_RT ? 0 : 1));
-      } else {
-        PAT_TRY(r.zfft(bf, 0));
-        PAT_TRY(r.spread(bf, bu, op == OP_RT ? 0 : 1));
-        PAT_TRY(r.a2t(bu, bg));
-      }
-      PAT_TRY(r.x2(bg, false, 1));
-      PAT_TRY(r.c2r(bg, out, false));
-      break;
+      if (fused) return r.nufft1(bf, bg, mode);
+      PAT_TRY(r.zfft(bf, 0));
+      PAT_TRY(r.spread(bf, bu, mode));
+      return r.a2t(bu, bg);
+    case 4: return r.x2(b, fwd, 1);
+    case 5: return r.c2r(b, out, fwd);
   }
   return hipSuccess;
 }
@@ -3337,20 +3366,86 @@ bool all_taps(int n, const Inst* h, int taps) {
   return true;
 }
 
+// Stage `stage` of an operator over n instances with one kernel build (the
+// radix set of their largest prime).
+template <typename T, typename G>
+hipError_t dispatch_one_build(Op op, int stage, int n, const Inst* h, const Inst* const* d, const void* const* hp,
+                              const void* const* in, void* const* out, void* const* ws, uint32_t* counters,
+                              int counter0, hipStream_t st, StageTimer* tm) {
+  const bool t12 = all_taps(n, h, 12);
+  if (all_pow2(n, h)) {
+    if (t12) return run_op_t<T, G, 0, 12>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+    return run_op_t<T, G, 0, 0>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+  }
+  if (max_radix(n, h) <= 8) {
+    if (t12) return run_op_t<T, G, 7, 12>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+    return run_op_t<T, G, 7, 0>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+  }
+  if (t12) return run_op_t<T, G, 23, 12>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+  return run_op_t<T, G, 23, 0>(op, stage, n, h, d, hp, in, out, ws, counters, counter0, st, tm);
+}
+
+// The radix class of an instance's FFT lengths: 0 powers of two, 1 radices up
+// to 8, 2 larger primes (the kernel build each class needs).
+int radix_class(const Inst& I) {
+  if (I.pow2) return 0;
+  return max_radix(1, &I) <= 8 ? 1 : 2;
+}
+
+// An operator over n instances.  Several instances are grouped by radix
+// class, so that every instance runs the kernel build its own lengths need
+// (one build over all would give every instance the registers of the largest
+// prime's butterflies); each stage then runs one persistent launch per class
+// present, all classes' stage s before any class's stage s + 1, so that only
+// the last stage writes the outputs.  A class of one instance takes the
+// single-instance kernels.  The work counters are cleared once, up front.
 template <typename T, typename G>
 hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
                     void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
-  const bool t12 = all_taps(n, h, 12);
-  if (all_pow2(n, h)) {
-    if (t12) return run_op_t<T, G, 0, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
-    return run_op_t<T, G, 0, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  if (counters) {
+    if (launch_faulted()) return hipErrorLaunchFailure;
+    if (tm) tm->begin("zero_counters", st);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters, kNumCounters);
+    PAT_TRY(hipGetLastError());
+    if (tm) tm->end(st);
   }
-  if (max_radix(n, h) <= 8) {
-    if (t12) return run_op_t<T, G, 7, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
-    return run_op_t<T, G, 7, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  if (n == 1) {
+    for (int stage = 1; stage <= 5; ++stage) {
+      const hipError_t e = dispatch_one_build<T, G>(op, stage, 1, h, d, hp, in, out, ws, counters, 0, st, tm);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  if (t12) return run_op_t<T, G, 23, 12>(op, n, h, d, hp, in, out, ws, counters, st, tm);
-  return run_op_t<T, G, 23, 0>(op, n, h, d, hp, in, out, ws, counters, st, tm);
+  struct Group {
+    int k = 0;
+    Inst h[kMaxBatch];
+    const Inst* d[kMaxBatch];
+    const void* hp[kMaxBatch];
+    const void* in[kMaxBatch];
+    void* out[kMaxBatch];
+    void* ws[kMaxBatch];
+  };
+  static thread_local Group g[3];
+  for (int c = 0; c < 3; ++c) g[c].k = 0;
+  for (int i = 0; i < n; ++i) {
+    Group& G_ = g[radix_class(h[i])];
+    const int k = G_.k++;
+    G_.h[k] = h[i];
+    G_.d[k] = d[i];
+    G_.hp[k] = hp[i];
+    G_.in[k] = in[i];
+    G_.out[k] = out[i];
+    G_.ws[k] = ws[i];
+  }
+  for (int stage = 1; stage <= 5; ++stage) {
+    for (int c = 0; c < 3; ++c) {
+      if (g[c].k == 0) continue;
+      const hipError_t e = dispatch_one_build<T, G>(op, stage, g[c].k, g[c].h, g[c].d, g[c].hp, g[c].in, g[c].out,
+                                                    g[c].ws, g[c].k == 1 ? nullptr : counters, 8 * c, st, tm);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 template <typename T, typename G>

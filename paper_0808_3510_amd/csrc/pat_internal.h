@@ -13,7 +13,7 @@ constexpr int kMaxBatch = 32;    // instances in one batched call
 constexpr int kMaxTaps = 64;     // 2cK
 constexpr double kMaxCutoff = 8.0;  // cut-off radius in sampling steps
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
-constexpr int kNumCounters = 16; // persistent work counters per batched call
+constexpr int kNumCounters = 32; // persistent work counters per batched call (8 per radix class)
 // Bytes of the static per-device scratch array behind the allocation-free
 // entry point (pat_reconstruct_noalloc); a plan whose workspace needs more is
 // refused there.

@@ -58,14 +58,28 @@ def test_injected_failures_batched_and_noalloc(fault_env):
           for i, pl in enumerate(plans)]
     ref, ws = pat.reconstruct_batched(plans, ps)
     ref = [r.clone() for r in ref]
-    for k in range(1, 7):  # the counter reset, then five stages
+    # The two instances fall into different kernel builds (radix classes):
+    # the counter reset, then each of the five stages once per class, the
+    # classes interleaved stage by stage.  Only the last stage writes the
+    # outputs, so a failure before it leaves every output untouched, and a
+    # failure within it leaves each output either untouched or complete.
+    k = 0
+    while True:
+        k += 1
         fault_env["PAT_FAULT"] = f"launch:{k}"
         outs = [torch.full_like(r, 5.0) for r in ref]
-        with pytest.raises(pat.PatError) as ei:
+        try:
             pat.reconstruct_batched(plans, ps, outs, ws)
-        assert ei.value.status == 4
+        except pat.PatError as e:
+            assert e.status == 4
+        else:
+            break
         torch.cuda.synchronize()
-        assert all(torch.all(o == 5.0) for o in outs), k
+        for o, r in zip(outs, ref):
+            assert torch.all(o == 5.0) or torch.equal(o, r), k
+        if k <= 1 + 4 * 2:
+            assert all(torch.all(o == 5.0) for o in outs), k
+    assert k == 1 + 5 * 2 + 1  # eleven launches; the twelfth never comes
     plan = plans[0]
     for mode in ("scratch", "launch:3"):
         fault_env["PAT_FAULT"] = mode
