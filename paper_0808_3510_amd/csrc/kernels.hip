@@ -2214,9 +2214,11 @@ template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
-  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
-  cx<T>* buf = tw + I.m;
-  if (new_inst_) load_twiddles(tw, I, I.fm);
+  // the twiddle table in LDS before the lines, or (long lines) read from memory
+  cx<T>* lds = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = I.twg_m ? lds : lds + I.m;
+  const cx<T>* tw = I.twg_m ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
+  if (new_inst_ && !I.twg_m) load_twiddles(lds, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
@@ -2255,9 +2257,11 @@ template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
   constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
-  cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
-  cx<T>* buf = tw + I.m;
-  if (new_inst_) load_twiddles(tw, I, I.fm);
+  // the twiddle table in LDS before the lines, or (long lines) read from memory
+  cx<T>* lds = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* buf = I.twg_m ? lds : lds + I.m;
+  const cx<T>* tw = I.twg_m ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
+  if (new_inst_ && !I.twg_m) load_twiddles(lds, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);

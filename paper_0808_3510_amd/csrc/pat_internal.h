@@ -54,6 +54,8 @@ struct Inst {
   int32_t centred;            // grid from centred samples (KB, sinc) or not (linear, nearest)
   int32_t fused;              // 1: line stages fused in LDS (grid never stored), 0: staged
   int32_t cut_e;              // cut-off band width E = ceil(2 eps) in samples; 0: no cut-off
+  int32_t twg_m;              // 1: the staged grid-line kernels read the c*nt-point twiddles from
+                              // memory (table and line together exceed LDS), 0: from LDS
   double c, K, alpha;
   double ck;                  // c*K
   // node and weight:  nu+^2 = a1 k1^2 + a2 k2^2 + b l^2 ;  W = wcoef |l| / nu+
@@ -88,7 +90,7 @@ inline size_t lds_tile_x1(const Inst& I, size_t cs) {
 }
 inline size_t lds_tile_x2(const Inst& I, size_t cs) { return (size_t)I.n2 * (I.tb + 1) * cs; }
 inline size_t lds_line_z(const Inst& I, size_t cs) { return (size_t)I.nz * (I.lpw_z + 1) * cs; }
-inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.m * (I.lpw_m + 1) * cs; }
+inline size_t lds_line_m(const Inst& I, size_t cs) { return (size_t)I.m * (I.lpw_m + (I.twg_m ? 0 : 1)) * cs; }
 // interp: lpw_i grid lines of m entries plus a halo of taps - 1
 inline size_t lds_interp(const Inst& I, size_t cs) { return (size_t)I.lpw_i * ((size_t)I.m + I.taps) * cs; }
 // streamed interp: one buffer of lpw_i lines, line stride m + taps - 1

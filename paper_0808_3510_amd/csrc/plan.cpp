@@ -371,7 +371,9 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   const int prec = g.precision;
   const size_t cs = complex_bytes(prec);
   const size_t rs = cs / 2;
-  if ((size_t)m * cs > 65536) {
+  // one grid line with its halo of taps must fit one workgroup's LDS (lines
+  // whose twiddle table does not fit beside them read it from memory)
+  if (((size_t)m + kMaxTaps) * cs > kLdsMax) {
     msg << "c*nt = " << m << " exceeds the LDS line capacity for this precision";
     return fail(PAT_ERR_UNSUPPORTED);
   }
@@ -409,6 +411,7 @@ pat_status build_plan(const pat_geometry& gin, pat_plan* p, std::string* err) {
   while (I.tb > 1 && std::max(lds_tile_x1(I, cs), lds_tile_x2(I, cs)) > 65536) I.tb /= 2;
   I.pow2 = is_pow2(n1) && is_pow2(n2) && is_pow2(m) && is_pow2(g.nz);
   I.lpw_m = clampi(2048 / m, 1, 16);
+  I.twg_m = (size_t)m * (I.lpw_m + 1) * cs > kLdsMax ? 1 : 0;
   I.lpw_z = clampi(2048 / g.nz, 1, 16);
   if (lds_line_z(I, cs) > kLdsMax) {
     msg << "nz = " << g.nz << " exceeds the LDS line capacity for this precision";

@@ -41,10 +41,11 @@ valid = [dict(), dict(n2=1), dict(precision="f64"), dict(precision="bf16grid"), 
          dict(c=4.0), dict(c=16.0, K=2.0, nt=64), dict(c=32.0, K=1.0, nt=16), dict(interp="linear", c=1.0),
          dict(interp="nearest", c=2.0), dict(interp="sinc", c=2.0), dict(cutoff=2.5), dict(cutoff=4.0, n2=1, nt=64),
          dict(n1=4096, n2=1, nt=8, nz=8), dict(nt=4096, nz=64, n1=2, n2=2), dict(nz=2048, nt=4096, n1=4, n2=1),
-         dict(n1=46, n2=38, nt=38, nz=34), dict(vs=1.7, dt=0.3, dz=0.9, dx=1.1)]
+         dict(nt=8192, nz=64, n1=2, n2=2), dict(c=32.0, K=1.0, nt=512, nz=64, n1=16, n2=1),
+         dict(c=16.0, K=2.0, nt=512, nz=64, n1=16, n2=1, precision="f64"), dict(n1=46, n2=38, nt=38, nz=34), dict(vs=1.7, dt=0.3, dz=0.9, dx=1.1)]
 invalid = [(dict(nt=31), 1), (dict(nz=0), 1), (dict(n1=15), 1), (dict(dx=0.0), 1), (dict(vs=float("inf")), 1),
            (dict(c=1.0), 1), (dict(K=1.3), 1), (dict(alpha=3.0), 1), (dict(precision=9), 1), (dict(n1=58), 2),
-           (dict(nt=16384), 2), (dict(nt=8192, nz=64, n1=2, n2=2), 2), (dict(nz=8192, precision="f64"), 2), (dict(interp=9), 1), (dict(cutoff=-1.0), 1),
+           (dict(nt=16384), 2), (dict(c=32.0, K=1.0, nt=512, nz=64, precision="f64"), 2), (dict(nz=8192, precision="f64"), 2), (dict(interp=9), 1), (dict(cutoff=-1.0), 1),
            (dict(cutoff=4.5), 1), (dict(K=32.0), 1), (dict(c=2.0, K=3.0, nt=4), 1)]
 
 plans = []

@@ -46,6 +46,7 @@ def test_valid_plan_sizes():
     (dict(n1=58), 2),            # 29 is not a supported FFT radix
     (dict(n1=8192, n2=2), 2), (dict(nt=16384), 2), (dict(K=32.0, c=2.0), 1),
     (dict(nz=8192, precision="f64"), 2),   # a double depth line pair exceeds LDS
+    (dict(c=32.0, K=1.0, nt=512, nz=64, precision="f64"), 2),  # a 16384-point double grid line exceeds LDS
     (dict(interp=7), 1), (dict(c=1.0, interp="kb"), 1), (dict(c=0.5, interp="linear"), 1),
     (dict(cutoff=-1.0), 1), (dict(cutoff=8.5, n1=64, n2=64, nt=64), 1), (dict(cutoff=float("nan")), 1),
     (dict(cutoff=4.5), 1),       # 4 eps exceeds the 16 detectors
@@ -124,3 +125,19 @@ def test_cutoff_plans_carry_a_weight_table(eps, n2):
     finally:
         pat.pat_plan_destroy(base)
         pat.pat_plan_destroy(cut)
+
+
+@pytest.mark.parametrize("kw", [dict(c=32.0, K=1.0, nt=512, nz=64), dict(c=16.0, K=2.0, nt=512, nz=64, precision="f64"),
+                                dict(nt=8192, nz=64, n1=2, n2=2)])
+def test_long_grid_lines_plan_staged_only(kw):
+    """Grid lines longer than the fused kernels' LDS share (16384 FP32 points:
+    c = 32 at nt = 512; 8192 FP64 points) are planned for the staged kernels,
+    and asking for the fused ones is refused."""
+    ptr = pat.pat_plan_create(_geom(**kw))
+    try:
+        with pytest.raises(pat.PatError) as ei:
+            pat.pat_plan_set_fused(ptr, True)
+        assert ei.value.status == 2
+        pat.pat_plan_set_fused(ptr, False)
+    finally:
+        pat.pat_plan_destroy(ptr)

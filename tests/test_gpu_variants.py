@@ -52,8 +52,10 @@ def test_methods_run_the_reconstruction_only():
 
 # Kaiser-Bessel over the oversampling factors of Fig. 5 and one step past
 # them (2cK taps capped at 64, so K = 2 at c = 16 and K = 1 at c = 32).  The
-# last geometry has an 8192-point grid line at c = 16: its fused kernel holds
-# 131 KB of LDS; at c = 32 its 16384-point line does not fit one workgroup.
+# last geometry has the paper's nt = 512: 8192-point grid lines at c = 16 (the
+# fused kernel holds 131 KB of LDS; in FP64 the line alone is 128 KB, staged)
+# and 16384-point lines at c = 32 (staged: one line per workgroup with its
+# twiddles read from memory; in FP64 such a line exceeds LDS).
 KB_SWEEP = [(4.0, 3.0), (8.0, 3.0), (16.0, 2.0), (32.0, 1.0)]
 KB_GEOS = GEOS[:2] + [dict(n1=16, n2=1, nt=512, nz=64, dx=1 / 16, dt=1 / 512, dz=1 / 64, vs=1.0)]
 
@@ -65,21 +67,43 @@ KB_GEOS = GEOS[:2] + [dict(n1=16, n2=1, nt=512, nz=64, dx=1 / 16, dt=1 / 512, dz
 def test_kaiser_bessel_oversampling_sweep(fused, prec, c, K, gi):
     g = KB_GEOS[gi]
     print(f"R kb c={c} K={K} {prec} fused={fused} {g}", flush=True)
-    if c * g["nt"] * (16 if prec == "f64" else 8) > 65536:
-        # a grid line beyond one workgroup's line capacity: plan creation
-        # refuses it before anything runs
+    mk = lambda: pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K,  # noqa: E731
+                          precision=prec, device="cuda")
+    m_bytes = c * g["nt"] * (16 if prec == "f64" else 8)
+    if m_bytes + 64 * (16 if prec == "f64" else 8) > 160 * 1024:
+        # one grid line beyond a workgroup's LDS: plan creation refuses it
         with pytest.raises(pat.PatError) as ei:
-            pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K,
-                     precision=prec, device="cuda")
+            mk()
         assert ei.value.status == 2
         return
+    plan = mk()
+    if fused and m_bytes > 64 * 1024:
+        # the fused kernels hold a line twice (FFT order and natural order)
+        with pytest.raises(pat.PatError) as ei:
+            plan.set_fused(True)
+        assert ei.value.status == 2
+        return
+    plan.set_fused(fused)
     shape = (g["n1"], g["n2"], g["nt"]) if g["n2"] > 1 else (g["n1"], g["nt"])
     p = inputs.random_array(shape, 500 + gi)
     expect = recon.reconstruct_with(p, g, "kb", c, K)
-    plan = pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=c, K=K,
-                    precision=prec, device="cuda")
-    plan.set_fused(fused)
     dt = torch.float64 if prec == "f64" else torch.float32
     f = plan.reconstruct(torch.from_numpy(p).to("cuda", dt))
     torch.cuda.synchronize()
     assert relerr(f.cpu().double().numpy(), expect) < TOL[prec]
+
+
+@pytest.mark.parametrize("kind", ["sinc", "linear", "nearest"])
+def test_other_methods_at_c32_nt512(kind):
+    """The oversampling c = 32 of Fig. 5 at the paper's nt = 512 (16384-point
+    grid lines) for the methods other than Kaiser-Bessel, against the oracle."""
+    g = KB_GEOS[2]
+    print(f"R {kind} c=32 {g}", flush=True)
+    p = inputs.random_array((g["n1"], g["nt"]), 510)
+    K = 1.0
+    expect = recon.reconstruct_with(p, g, kind, 32.0, K)
+    plan = pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], c=32.0, K=K,
+                    precision="f32", device="cuda", interp=kind)
+    f = plan.reconstruct(torch.from_numpy(p).to("cuda", torch.float32))
+    torch.cuda.synchronize()
+    assert relerr(f.cpu().double().numpy(), expect) < TOL["f32"]
