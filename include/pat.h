@@ -120,12 +120,19 @@ typedef enum {
  *            w R^T(q), w A(f), A^T(w p).  0 < eps <= 8 and 4 eps <= every
  *            data axis length (n1, n2 in 3D, nt), else PAT_ERR_INVALID_ARG.
  * Every FFT length (nx[0], nx[1], nz, c*nt) must factor into primes <= 23.
- * A line of c*nt (and of nz) complex values must fit one workgroup's LDS:
- * c*nt <= 8192 in float, 4096 in double; larger sizes make pat_plan_create
- * return PAT_ERR_UNSUPPORTED.  The operators that spread (reconstruct
- * adjoint, forward model, nufft1_lines) also keep per-node lists of a depth
- * line in LDS, which bounds nz to about 1800 in float and 900 in double;
- * beyond that those calls return PAT_ERR_UNSUPPORTED.
+ * A line of c*nt complex values with a halo of 64 taps must fit one
+ * workgroup's LDS (160 KB): c*nt <= 20416 in float, 10176 in double (16384
+ * and 8192 among the powers of two); the fused line kernels hold a line
+ * twice, plus per-node lists, so about half of that (c*nt = 8192 in float
+ * and 4096 in double fit; larger plans run the staged kernels, and pat_plan_set_fused(plan, 1) returns
+ * PAT_ERR_UNSUPPORTED for them).  A depth line pair (2 nz values) must fit
+ * as well, nz <= 5120 in double.  Larger sizes make
+ * pat_plan_create return PAT_ERR_UNSUPPORTED.  The operators that spread
+ * (reconstruct adjoint, forward model, nufft1_lines) also keep per-node
+ * lists of a depth line in LDS, (nz + 2) * (8 + 4 + 4 r) bytes in float and
+ * (nz + 2) * (16 + 4 + 8 r) in double with r = (2cK + 6) | 1: nz up to
+ * about 1800 (float) and 900 (double) at 12 taps; beyond that those calls
+ * return PAT_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t ndim;
@@ -201,10 +208,14 @@ pat_status pat_forward(pat_plan* plan, const void* f, size_t f_bytes, void* p, s
 pat_status pat_forward_adjoint(pat_plan* plan, const void* p, size_t p_bytes, void* f, size_t f_bytes, void* ws,
                                size_t ws_bytes, void* stream);
 
-/* R for n independent plans (1 <= n <= 32) in one launch per stage: work
- * items (instance, tile or line) are drawn from a device work counter by a
- * persistent grid.  All plans must share one precision.  p[i], f[i] as for
- * pat_reconstruct of plans[i]; ws of pat_batched_workspace_size() bytes. */
+/* R for n independent plans (1 <= n <= 32).  The plans are grouped by the
+ * radix class of their FFT lengths (the butterflies a kernel build carries);
+ * each group runs one launch per stage, whose persistent grid draws work
+ * items (instance, tile or line) from a device work counter, and the groups'
+ * launches are interleaved stage by stage on the stream.  All plans must
+ * share one precision.  p[i], f[i] as for pat_reconstruct of plans[i]; ws of
+ * pat_batched_workspace_size() bytes.  If a launch fails, each f[i] is
+ * either complete or untouched. */
 pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes);
 pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p,
                                    const size_t* p_bytes, void* const* f, const size_t* f_bytes, void* ws,
