@@ -124,15 +124,15 @@ typedef enum {
  * workgroup's LDS (160 KB): c*nt <= 20416 in float, 10176 in double (16384
  * and 8192 among the powers of two); the fused line kernels hold a line
  * twice, plus per-node lists, so about half of that (c*nt = 8192 in float
- * and 4096 in double fit; larger plans run the staged kernels, and pat_plan_set_fused(plan, 1) returns
- * PAT_ERR_UNSUPPORTED for them).  A depth line pair (2 nz values) must fit
- * as well, nz <= 5120 in double.  Larger sizes make
- * pat_plan_create return PAT_ERR_UNSUPPORTED.  The operators that spread
- * (reconstruct adjoint, forward model, nufft1_lines) also keep per-node
- * lists of a depth line in LDS, (nz + 2) * (8 + 4 + 4 r) bytes in float and
- * (nz + 2) * (16 + 4 + 8 r) in double with r = (2cK + 6) | 1: nz up to
- * about 1800 (float) and 900 (double) at 12 taps; beyond that those calls
- * return PAT_ERR_UNSUPPORTED.
+ * and 4096 in double fit; larger plans run the staged kernels, and
+ * pat_plan_set_fused(plan, 1) returns PAT_ERR_UNSUPPORTED for them).  A
+ * depth line pair (2 nz values) must fit as well, nz <= 5120 in double.
+ * Larger sizes make pat_plan_create return PAT_ERR_UNSUPPORTED.  The
+ * operators that spread (reconstruct adjoint, forward model, nufft1_lines)
+ * also keep per-node lists of a depth line in LDS, (nz + 2) * (8 + 4 + 4 r)
+ * bytes in float and (nz + 2) * (16 + 4 + 8 r) in double with r = (2cK + 6)
+ * | 1: nz up to about 1800 (float) and 900 (double) at 12 taps; beyond that
+ * those calls return PAT_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t ndim;
