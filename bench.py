@@ -393,11 +393,27 @@ def oracle_parity(p_np, g, outputs, keep, np):
 KERNEL_OF_STAGE = {
     # library stage name -> kernel symbol prefixes in the profiler's output
     "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<", "void pat::k_line_nufft2_pipe_c<"),
-    "nufft_adjoint_fused": ("void pat::k_line_nufft1<", "void pat::k_line_nufft1_c<"),
+    "nufft_adjoint_fused": ("void pat::k_line_nufft1<", "void pat::k_line_nufft1_c<", "void pat::k_line_nufft1_w<"),
     "dft_x1": ("void pat::k_tr_x1_r2c<", "void pat::k_tr_x1_pipe<"),
     "dft_x2": ("void pat::k_tr_x2<", "void pat::k_tr_x2_pipe<"),
     "idft_x1_c2r": ("void pat::k_tr_c2r_k1<", "void pat::k_tr_c2r_pipe<"),
+    "interp": ("void pat::k_line_interp<", "void pat::k_line_interp_stream<"),
+    "spread": ("void pat::k_line_spread<", "void pat::k_line_spread_w<"),
 }
+
+
+def traffic_of(stage, workload, precision):
+    """HBM bytes per launch of a stage from profiles/traffic.json, or None
+    when there is none or the kernel sources changed since it was taken."""
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tfile):
+        return None
+    with open(tfile) as fh:
+        t = json.load(fh)
+    key = f"{stage}:{workload}:{precision}"
+    if t.get("kernel_source") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(key)
 
 
 def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision, out_path=None):
@@ -465,6 +481,67 @@ def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision,
     return out
 
 
+def counters_summary(counter_csvs, trace_csv, workload):
+    """Markdown table of the SQ counters of each stage's kernels from
+    rocprofv3 --pmc runs (one csv per pass) and the kernel durations from a
+    --kernel-trace run of the same command.  Counters are summed over the
+    GPU per dispatch and averaged over the dispatches of one kernel and grid.
+    VALU busy is the share of SIMD cycles that issue VALU: 4 cycles per wave
+    instruction (64 lanes on a 16-lane SIMD) over 1024 SIMDs at 2.4 GHz."""
+    import csv
+
+    def key_of(name):
+        for stage, prefixes in KERNEL_OF_STAGE.items():
+            if name.startswith(prefixes):
+                return stage
+        return None
+
+    vals = {}  # (kernel, grid) -> counter -> [per-dispatch sums]
+    for path in counter_csvs:
+        acc, names = {}, {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                d = int(r.get("Dispatch_Id", r.get("Correlation_Id", "0")))
+                acc[(d, r["Counter_Name"])] = acc.get((d, r["Counter_Name"]), 0.0) + float(r["Counter_Value"])
+                names[d] = (r["Kernel_Name"], int(r["Grid_Size"]))
+        for (d, c), v in acc.items():
+            vals.setdefault(names[d], {}).setdefault(c, []).append(v)
+    dur = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            k = (r["Kernel_Name"], int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0))
+            dur.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    rows = []
+    for (name, grid), cs in sorted(vals.items()):
+        stage = key_of(name)
+        if stage is None:
+            continue
+        avg = {c: sum(v) / len(v) for c, v in cs.items()}
+        ds = dur.get((name, grid)) or [t for (n, _), ts in dur.items() if n == name for t in ts]
+        sec = sum(ds) / len(ds) if ds else None
+        waves = avg.get("SQ_WAVES")
+        per_wave = lambda c: f"{avg[c] / waves:.0f}" if c in avg and waves else "-"  # noqa: E731
+        busy = (4 * avg["SQ_INSTS_VALU"] / (1024 * 2.4e9 * sec)) if sec and "SQ_INSTS_VALU" in avg else None
+        lds_conf = (avg["SQ_LDS_BANK_CONFLICT"] / avg["SQ_ACTIVE_INST_LDS"]
+                    if avg.get("SQ_ACTIVE_INST_LDS") and "SQ_LDS_BANK_CONFLICT" in avg else None)
+        rows.append((stage, name.split("(")[0].replace("void ", ""), grid, len(next(iter(cs.values()))),
+                     sec * 1e6 if sec else None, waves, per_wave("SQ_INSTS_VALU"), per_wave("SQ_INSTS_LDS"),
+                     per_wave("SQ_INSTS_SALU"), per_wave("SQ_INSTS_VMEM_RD"), per_wave("SQ_INSTS_VMEM_WR"), busy,
+                     lds_conf))
+    lines = [f"Counters per dispatch, workload {workload}:", "",
+             "| stage | kernel | grid | dispatches | avg us | waves | VALU/wave | LDS/wave | SALU/wave | "
+             "VMEM rd/wave | VMEM wr/wave | VALU busy | LDS conflict cycles per LDS cycle |",
+             "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append("| " + " | ".join([r[0], f"`{r[1]}`", str(r[2]), str(r[3]),
+                                        f"{r[4]:.1f}" if r[4] else "-", f"{r[5]:.0f}" if r[5] else "-",
+                                        *r[6:11], f"{r[11]:.2f}" if r[11] is not None else "-",
+                                        f"{r[12]:.2f}" if r[12] is not None else "-"]) + " |")
+    text = "\n".join(lines)
+    print(text)
+    return text
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -479,9 +556,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
+    ap.add_argument("--counters-from", nargs="+", metavar="CSV",
+                    help="print the SQ counter table from rocprofv3 --pmc csvs; the last csv is the "
+                         "--kernel-trace csv of the same command (no GPU work)")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_BYTES"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files (no GPU work)")
     args = ap.parse_args()
+    if args.counters_from:
+        counters_summary(args.counters_from[:-1], args.counters_from[-1], args.workload)
+        return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], int(args.traffic_from[2]), args.workload,
                               args.precision)
@@ -536,14 +619,7 @@ def main():
     phantom = inputs.ball_volume(balls, n, n, nz, g["dx"], g["dz"])
     rel_phantom = float(np.linalg.norm(f_host - phantom) / np.linalg.norm(phantom))
 
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            t = json.load(fh)
-        key = f"{dom}:{args.workload}:{args.precision}"
-        if t.get("kernel_source") == kernel_source_hash() and key in t.get("bytes_per_launch", {}):
-            traffic = t["bytes_per_launch"][key]
+    traffic = traffic_of(dom, args.workload, args.precision)
 
     out = {
         "metric": "voxels/s per full reconstruction; NUFFT pts/s; FP32 vs FP64 at relL2<=1e-5",
@@ -593,7 +669,8 @@ def main():
         out["adjoint_roofline"] = dict(
             roofline_of("nufft_adjoint_fused", stage_bytes("nufft_fused", n, n, nt, nz, m, args.precision),
                         stage_flops("nufft_adjoint_fused", n, n, nt, nz, m), adj_ms),
-            kernel="nufft_adjoint_fused", avg_launch_ms=adj_ms)
+            kernel="nufft_adjoint_fused", avg_launch_ms=adj_ms,
+            traffic=traffic_of("nufft_adjoint_fused", args.workload, args.precision))
     del plan, f, q, pt
     # R with the smooth cut-off of the partial-data model (eps = 4 steps):
     # the weights are applied inside the first transverse pass

@@ -338,9 +338,14 @@ __device__ __forceinline__ void twiddle_pow2(cx<T>* v, cx<T> w1) {
   for (int d = 1; d < R; ++d) v[d] = cmul(v[d], w[d]);
 }
 
-template <typename T, int R, bool P2, bool BF, typename Ptr = cx<T>*>
+// With PADL > 0 the scratch is padded: element i sits at i + (i >> PADL), one
+// spare slot after every 2^PADL points, so that the strided butterfly
+// accesses of the later stages (lanes 2^PADL points apart) spread over the
+// LDS banks (power-of-two radices only).
+template <typename T, int R, bool P2, bool BF, typename Ptr = cx<T>*, int PADL = 0>
 __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* __restrict__ tw, int nb,
                                           int bs, int es) {
+  static_assert(PADL == 0 || R == 2 || R == 4 || R == 8 || R == 16, "padded scratch: power-of-two radices");
   const int sub = Li / R;
   const int tws = L / Li;
   const int nbf = L / R;
@@ -381,17 +386,28 @@ __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* _
       blk = bf / sub;
       j = bf - blk * sub;
     }
-    Ptr p = buf + b * bs + (blk * Li + j) * es;
+    const int i0 = b * bs + (blk * Li + j) * es;
+    Ptr p = buf + i0;
     const int st = sub * es;
+    // (strides that are multiples of 2^PADL keep a constant padded stride)
+    const int pst = PADL > 0 && st % (1 << PADL) == 0 ? st + (st >> PADL) : 0;
+    Ptr pp = PADL > 0 ? buf + (i0 + (i0 >> PADL)) : p;
+    auto at = [&](int r) {
+      if constexpr (PADL > 0) {
+        const int i = i0 + r * st;
+        return pst ? pp + r * pst : buf + (i + (i >> PADL));
+      }
+      return p + r * st;
+    };
     if constexpr (R == 2 || R == 4 || R == 8) {
       cx<T> v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = ldx(p + r * st);
+      for (int r = 0; r < R; ++r) v[r] = ldx(at(r));
       dft_pow2<T, R>(v);
       // (the last stage, sub = 1, has j = 0 and no twiddles)
       if (sub > 1) twiddle_pow2<T, R>(v, tw[j * tws]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) stx(p + r * st, v[r]);
+      for (int r = 0; r < R; ++r) stx(at(r), v[r]);
     } else {
       bfly_prime<T, R>(p, st, j, tws, tw, L);
     }
@@ -472,7 +488,7 @@ __device__ __forceinline__ int dif_natural_p2(const FftDesc& d, int pos) {
 // The last stage (sub = 1, no twiddles) of a power-of-two DIF transform,
 // handing each butterfly's R outputs (positions blk*R + r) to
 // sink(b, blk, v) instead of writing them back.
-template <typename T, int R, bool BF, typename Sink>
+template <typename T, int R, bool BF, int PADL = 0, typename Sink>
 __device__ __forceinline__ void fft_last_stage_p2(const cx<T>* buf, int L, int nb, int bs, int es, Sink sink) {
   const int nbf = L / R;
   const int lnbf = __builtin_ctz((unsigned)nbf), lnb = __builtin_ctz((unsigned)nb);
@@ -485,10 +501,20 @@ __device__ __forceinline__ void fft_last_stage_p2(const cx<T>* buf, int L, int n
       b = id & (nb - 1);
       blk = id >> lnb;
     }
-    const cx<T>* p = buf + b * bs + blk * R * es;
+    // (padded: a run of R <= 2^PADL points from a multiple of R stays in one
+    // padded block when es = 1)
+    const int i0 = b * bs + blk * R * es;
+    const cx<T>* p = buf + (PADL > 0 ? i0 + (i0 >> PADL) : i0);
     cx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = p[r * es];
+    for (int r = 0; r < R; ++r) {
+      if constexpr (PADL > 0) {
+        const int i = i0 + r * es;
+        v[r] = es == 1 && R <= (1 << PADL) ? p[r] : buf[i + (i >> PADL)];
+      } else {
+        v[r] = p[r * es];
+      }
+    }
     dft_pow2<T, R>(v);
     sink(b, blk, v);
   }
@@ -600,13 +626,14 @@ static_assert(P2Plan<10, true>::nst == 3 && P2Plan<10, true>::rad(1) == 8 && P2P
 
 // Stages S .. nst - 2 (twiddled, in place) of the compile-time plan of 2^E
 // points on nb lines of stride 2^E, one block barrier after each.
-template <typename T, int E, int S, bool L16 = false>
+// (PADL: the padded scratch of fft_stage.)
+template <typename T, int E, int S, bool L16 = false, int PADL = 0>
 __device__ __forceinline__ void p2_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int nb) {
   using Pl = P2Plan<E, L16>;
   if constexpr (S + 1 < Pl::nst) {
-    fft_stage<T, Pl::rad(S), true, true>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
+    fft_stage<T, Pl::rad(S), true, true, cx<T>*, PADL>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
     __syncthreads();
-    p2_stages<T, E, S + 1, L16>(buf, tw, nb);
+    p2_stages<T, E, S + 1, L16, PADL>(buf, tw, nb);
   }
 }
 
@@ -996,17 +1023,37 @@ __device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m,
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
     const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
-    *vp = cmul(taps_at<T, TAPS, HALO>(U, m, wrap_tap<P2>(j0, m, inv_m), w), ph);
-    *vn = cmul(taps_at<T, TAPS, HALO>(U, m, wrap_tap<P2>(jm, m, inv_m), wm), cconj(ph));
+    const int jp = wrap_tap<P2>(j0, m, inv_m), jn = wrap_tap<P2>(jm, m, inv_m);
+    cx<T> sp, sn;
+    if (HALO || (jp <= m - TAPS && jn <= m - TAPS)) {
+      // both windows in one loop: two independent sums, two reads in flight
+      const cx<T>* up = U + jp;
+      const cx<T>* un = U + jn;
+      sp = sn = mk(T(0), T(0));
+#pragma unroll
+      for (int t = 0; t < TAPS; ++t) {
+        const cx<T> g = up[t], h = un[t];
+        sp.x += w[t] * g.x;
+        sp.y += w[t] * g.y;
+        sn.x += wm[t] * h.x;
+        sn.y += wm[t] * h.y;
+      }
+    } else {
+      sp = taps_at<T, TAPS, HALO>(U, m, jp, w);
+      sn = taps_at<T, TAPS, HALO>(U, m, jn, wm);
+    }
+    *vp = cmul(sp, ph);
+    *vn = cmul(sn, cconj(ph));
   } else {
     *vp = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, nup, I, a), ph);
     *vn = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, -nup, I, a), cconj(ph));
   }
 }
 
+template <bool P2 = false>
 __device__ __forceinline__ double line_ak(const Inst& I, int line) {
   int k1, k2i;
-  divmod<false>(line, I.n2, &k1, &k2i);
+  divmod<P2>(line, I.n2, &k1, &k2i);
   const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
   return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
 }
@@ -2654,8 +2701,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
   const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
   const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
   const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
-  cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);  // FFT scratch, later the depth lines
-  cx<T>* gn = gp + lpw * m;                          // grid lines in natural order
+  // grid lines in natural order at the start of LDS (the tap reads then take
+  // their offsets as immediates), then the FFT scratch (later the depth
+  // lines), padded by one point every 16: its strided stages spread over the
+  // LDS banks
+  constexpr int PADL = 4;
+  auto pad = [](int i) { return i + (i >> PADL); };
+  cx<T>* gn = reinterpret_cast<cx<T>*>(pat_smem);
+  cx<T>* gp = gn + lpw * m;
   const T* sn = static_cast<const T*>(I.sn);
   const int q = nt >> 2;
   // inputs r = 0, 1, 6, 7 of the butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
@@ -2690,12 +2743,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
       v[7] = cscl(pre[3], snr[3]);
       dft_pow2<T, 8>(v);
       twiddle_pow2<T, 8>(v, w1);
-      cx<T>* p = gp + bb * m + j;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) p[r * sub] = v[r];
+      for (int r = 0; r < 8; ++r) gp[pad(bb * m + j + r * sub)] = v[r];
     }
     __syncthreads();
-    p2_stages<T, LM, 1, p2_l16_m(LM)>(gp, twm, lpw);
+    p2_stages<T, LM, 1, p2_l16_m(LM), PADL>(gp, twm, lpw);
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
     auto sink = [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
@@ -2704,15 +2756,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) g[k0 + r * step] = v[r];
     };
-    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true>(gp, m, lpw, m, 1, sink);
+    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true, PADL>(gp, m, lpw, m, 1, sink);
     __syncthreads();
     cx<T>* fz = gp;
-    interp_lines<T, TAPS, true, true, false>(I, a, gn, m, [&](int b) { return line_ak(I, line0 + b); }, nl, a.mode,
-                                             [&](int e, cx<T> v) { fz[e] = cconj(v); });
+    interp_lines<T, TAPS, true, true, false>(I, a, gn, m, [&](int b) { return line_ak<true>(I, line0 + b); }, nl, a.mode,
+                                             [&](int e, cx<T> v) { fz[pad(e)] = cconj(v); });
     __syncthreads();
     cx<T>* out = outb + (size_t)line0 * nz;
-    p2_stages<T, LZ, 0, p2_l16_z(LZ)>(fz, twz, lpw);
-    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true>(fz, nz, lpw, nz, 1, [&](int b, int blk, const auto& v) {
+    p2_stages<T, LZ, 0, p2_l16_z(LZ), PADL>(fz, twz, lpw);
+    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true, PADL>(fz, nz, lpw, nz, 1, [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       if (b >= nl) return;
       cx<T>* o = out + b * nz;
@@ -3233,8 +3285,9 @@ struct Runner {
       const Inst& I = h[0];
       if (n == 1 && !a.counter && a.pair_ok && I.m == 2 * I.nt && I.m >= I.nz && I.fm.nst >= 2 &&
           I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock) {
-        // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2
-        const size_t shm = lds_fused2(I, cs);
+        // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2 (with
+        // the padded scratch)
+        const size_t shm = lds_fused2(I, cs) + (size_t)I.lpw_f * (I.m / 16) * cs;
         const int lm = __builtin_ctz((unsigned)I.m), dz = lm - __builtin_ctz((unsigned)I.nz);
         auto go = [&](auto kern) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm); };
         if (dz == 2) {
