@@ -213,7 +213,9 @@ def batched_and_small(steps, torch, dev, pat, inputs, np, keep=None):
 # the window's range (deconvolving on [-pi, pi] needs alpha > pi, Section 3.2
 # bounds alpha below pi (2c - 1)); past c = 8 the 2cK taps are capped at 64,
 # so K shrinks.
-KB_SWEEP = [("kb", 2.0, 3.0), ("kb", 4.0, 3.0), ("kb", 8.0, 3.0), ("kb", 16.0, 2.0)]
+# Fig. 5's oversampling factors and one step past them; 2cK <= 64 taps
+KB_SWEEP = [("kb", 2.0, 3.0), ("kb", 4.0, 3.0), ("kb", 8.0, 3.0), ("kb", 16.0, 2.0), ("kb", 32.0, 1.0)]
+C_SWEEP = (1, 2, 4, 8, 16, 32)
 
 
 def interpolation_study(p_np, g, steps, torch, dev, pat, np):
@@ -234,8 +236,10 @@ def interpolation_study(p_np, g, steps, torch, dev, pat, np):
     rows = []
     for kind, c, K, fused in [(k, c, K, True) for k, c, K in KB_SWEEP] + [("kb", 2.0, 3.0, False),
                                                                        ("sinc", 2.0, 3.0, False)] + \
-            [(k, float(c), 3.0, False) for k in ("linear", "nearest") for c in (1, 2, 4, 8, 16)]:
+            [(k, float(c), 3.0, False) for k in ("linear", "nearest") for c in C_SWEEP]:
         plan = plan_of(kind, c, "f32", K)
+        if fused and not plan.fusable:
+            fused = False  # (grid lines beyond the fused kernels' LDS share)
         plan.set_fused(fused)
         f = plan.reconstruct(p32)
         for _ in range(2):
@@ -271,7 +275,7 @@ def circle_experiment(steps, torch, dev, pat, inputs, np):
     p32 = torch.from_numpy(p0).to(dev, torch.float32)
     rows = []
     for kind, c, K in KB_SWEEP + [("sinc", 2.0, 3.0)] + [(k, float(c), 3.0) for k in ("linear", "nearest")
-                                                         for c in (1, 2, 4, 8, 16)]:
+                                                         for c in C_SWEEP]:
         plan = plan_of(kind, c, "f32", K)
         f = plan.reconstruct(p32)
         for _ in range(2):
@@ -469,8 +473,9 @@ def traffic_from_counters(fetch_csv, write_csv, copy_bytes, workload, precision,
         for (name, grid, sc), ds in sorted(groups.items(), key=lambda kv: (kv[0][2], kv[0][1])):
             f_avg = sum(fetch[d] for d in ds) / len(ds)
             w_avg = sum(write[d] for d in ds) / len(ds)
-            key = f"{stage}:{workload}:{precision}" + (f"[{name.split('<')[0].split('::')[-1]},grid={grid},"
-                                                       f"class={sc}]" if len(groups) > 1 else "")
+            short = name.split("(")[0].replace("void ", "").replace("pat::", "")
+            key = f"{stage}:{workload}:{precision}" + (f"[{short},grid={grid},class={sc}]" if len(groups) > 1
+                                                       else "")
             out["raw_kib_per_launch"][key] = {"fetch": f_avg, "write": w_avg, "dispatches": len(ds),
                                               "grid_threads": grid, "kernel": name}
             out["bytes_per_launch"][key] = 1024.0 * (f_avg * f_scale + w_avg * w_scale)
@@ -556,6 +561,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES bytes first (scale for HBM counters)")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="time a plain device copy and fill of BYTES (the HBM reference) and exit")
     ap.add_argument("--counters-from", nargs="+", metavar="CSV",
                     help="print the SQ counter table from rocprofv3 --pmc csvs; the last csv is the "
                          "--kernel-trace csv of the same command (no GPU work)")
@@ -585,6 +592,25 @@ def main():
     nt, nz = g["nt"], g["nz"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_ref > 0:
+        # the practical HBM rate: torch's copy (read + write) and fill (write)
+        a = torch.ones(args.copy_ref // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        res = {}
+        for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * args.copy_ref),
+                                 ("fill", lambda: b.fill_(1.0), args.copy_ref)):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / 20
+            res[name] = {"bytes": nbytes, "us": sec * 1e6, "GBs": nbytes / sec / 1e9}
+        print(json.dumps({"copy_reference": res}))
+        return
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

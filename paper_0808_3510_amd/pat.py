@@ -238,6 +238,13 @@ class Plan:
         self.table = torch.empty(tb, dtype=torch.uint8, device=self.device)
         pat_plan_upload(self.ptr, self.table.data_ptr(), tb, _stream(self.device))
         self.ws = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        # a new plan runs the fused line kernels when it can; asking for them
+        # again is a no-op there and refused elsewhere
+        try:
+            pat_plan_set_fused(self.ptr, True)
+            self.fusable = True
+        except PatError:
+            self.fusable = False
 
     def __del__(self):
         ptr = getattr(self, "ptr", None)

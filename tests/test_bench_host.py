@@ -64,3 +64,39 @@ def test_traffic_scales_pairs_and_groups(tmp_path):
     assert len(x2) == 2   # the two line lengths are told apart despite one grid size
     assert sorted(x2.values()) == pytest.approx(sorted([1024 * (66000 * 2 + 132096), 1024 * (33000 * 2 + 66048)]))
     assert json.load(open(o)) == json.loads(json.dumps(out))
+
+
+def test_counter_table_per_wave_and_busy(tmp_path):
+    """`bench.py --counters-from`: block rows of a dispatch are summed,
+    dispatches averaged, instructions divided by waves, VALU busy from the
+    traced duration (4 cycles per wave instruction over 1024 SIMDs at
+    2.4 GHz), LDS conflicts per active LDS cycle."""
+    b = _bench()
+    p1, p2, tr = tmp_path / "p1.csv", tmp_path / "p2.csv", tmp_path / "t.csv"
+    rows1 = []
+    for d in (7, 8):
+        rows1 += [(d, FUSED, 4096, [2048.0, 2048.0])]
+    _write(p1, "SQ_WAVES", rows1)
+    with open(p1, "a", newline="") as fh:
+        w = csv.writer(fh)
+        for d in (7, 8):
+            w.writerow([d, FUSED, 4096, "SQ_INSTS_VALU", 4096 * 1000.0])
+            w.writerow([d, FUSED, 4096, "SQ_LDS_BANK_CONFLICT", 300.0])
+            w.writerow([d, FUSED, 4096, "SQ_ACTIVE_INST_LDS", 200.0])
+    _write(p2, "SQ_INSTS_VALU_FLOPS_FP32", [(7, FUSED, 4096, [1.0]), (8, FUSED, 4096, [1.0])])
+    # 100 us per dispatch
+    with open(tr, "w", newline="") as fh:
+        w = csv.DictWriter(fh, ["Kernel_Name", "Grid_Size", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for t0 in (0, 10 ** 6):
+            w.writerow({"Kernel_Name": FUSED, "Grid_Size": 4096, "Start_Timestamp": t0,
+                        "End_Timestamp": t0 + 100000})
+    text = b.counters_summary([str(p1), str(p2)], str(tr), "wl")
+    row = [l for l in text.splitlines() if "k_line_nufft2_pipe<float, 12>" in l][0].split("|")
+    cells = [c.strip() for c in row[1:-1]]
+    assert cells[0] == "nufft_fused" and cells[3] == "2"       # stage, dispatches
+    assert cells[4] == "100.0" and cells[5] == "4096"          # avg us, waves
+    assert cells[6] == "1000"                                  # VALU per wave
+    busy = 4 * 4096 * 1000.0 / (1024 * 2.4e9 * 100e-6)
+    assert cells[11] == f"{busy:.2f}"
+    assert cells[12] == "1.50"
