@@ -211,10 +211,15 @@ pat_status pat_forward_adjoint(pat_plan* plan, const void* p, size_t p_bytes, vo
 /* R for n independent plans (1 <= n <= 32).  The plans are grouped by the
  * radix class of their FFT lengths (the butterflies a kernel build carries);
  * each group runs one launch per stage, whose persistent grid draws work
- * items (instance, tile or line) from a device work counter, and the groups'
- * launches are interleaved stage by stage on the stream.  All plans must
- * share one precision.  p[i], f[i] as for pat_reconstruct of plans[i]; ws of
- * pat_batched_workspace_size() bytes.  If a launch fails, each f[i] is
+ * items (instance, tile or line) from a device work counter.  The first group
+ * runs on `stream`; the others run on two streams of plans[0]'s own (created
+ * on its first batched call with the default priority, released by
+ * pat_plan_destroy), forked from `stream` after the work counters are
+ * cleared and joined back into it before the call returns, so that work the
+ * caller enqueues on `stream` afterwards sees every output.  With timing on
+ * (pat_plan_set_timing on plans[0]) everything runs on `stream`.  All plans
+ * must share one precision.  p[i], f[i] as for pat_reconstruct of plans[i];
+ * ws of pat_batched_workspace_size() bytes.  If a launch fails, each f[i] is
  * either complete or untouched. */
 pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t* workspace_bytes);
 pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p,

@@ -161,6 +161,16 @@ pat_status run(pat_plan* plan, pat::Op op, const void* in, size_t in_bytes, void
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Releases fork streams (HIP errors ignored: this also runs at process exit).
+void destroy_fork(pat::ForkStreams* f) {
+  if (!f) return;
+  for (auto& st : f->s)
+    if (st) (void)hipStreamDestroy(st);
+  for (auto& ev : f->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  delete f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,6 +278,24 @@ pat_status pat_batched_workspace_size(int32_t n, pat_plan* const* plans, size_t*
   return PAT_OK;
 }
 
+// The fork streams of the batched calls whose first plan this is, created on
+// the first such call (default priority, non-blocking); nullptr if HIP
+// refuses them, and the call then runs on the caller's stream alone.
+static const pat::ForkStreams* fork_of(pat_plan* plan) {
+  if (plan->fork) return static_cast<const pat::ForkStreams*>(plan->fork);
+  auto* f = new pat::ForkStreams;
+  bool ok = true;
+  for (auto& s : f->s) ok = ok && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+  for (auto& e : f->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    destroy_fork(f);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  plan->fork = f;
+  return f;
+}
+
 pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void* const* p, const size_t* p_bytes,
                                    void* const* f, const size_t* f_bytes, void* ws, size_t ws_bytes, void* stream) {
   if (!plans || !p || !f || !p_bytes || !f_bytes) return set_err(PAT_ERR_INVALID_ARG, "NULL argument");
@@ -302,8 +330,9 @@ pat_status pat_reconstruct_batched(int32_t n, pat_plan* const* plans, const void
     off += align256(plans[i]->ws_bytes);
   }
   arm_faults();
+  pat::StageTimer* tm = timer_of(plans[0]);
   hipError_t e = pat::run_op(plans[0]->prec, pat::OP_R, n, h, d, hp, p, f, wsi, counters,
-                             static_cast<hipStream_t>(stream), timer_of(plans[0]));
+                             static_cast<hipStream_t>(stream), tm, n > 1 && !tm ? fork_of(plans[0]) : nullptr);
   if (e != hipSuccess) return hip_err(e, "kernel launch");
   return PAT_OK;
 }
@@ -383,6 +412,7 @@ pat_status pat_plan_stage_times(pat_plan* plan, int32_t cap, const char** names,
 
 void pat_plan_destroy(pat_plan* plan) {
   if (!plan) return;
+  destroy_fork(static_cast<pat::ForkStreams*>(plan->fork));
   delete static_cast<EventTimer*>(plan->timer);
   delete plan;
 }

@@ -3458,7 +3458,8 @@ int radix_class(const Inst& I) {
 // single-instance kernels.  The work counters are cleared once, up front.
 template <typename T, typename G>
 hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const void* const* hp, const void* const* in,
-                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm) {
+                    void* const* out, void* const* ws, uint32_t* counters, hipStream_t st, StageTimer* tm,
+                    const ForkStreams* fork) {
   if (counters) {
     if (launch_faulted()) return hipErrorLaunchFailure;
     if (tm) tm->begin("zero_counters", st);
@@ -3494,15 +3495,49 @@ hipError_t dispatch(Op op, int n, const Inst* h, const Inst* const* d, const voi
     G_.out[k] = out[i];
     G_.ws[k] = ws[i];
   }
-  for (int stage = 1; stage <= 5; ++stage) {
+  // With the plan's fork streams (and no timer), each class after the first
+  // runs on a stream of its own, forked from st after the counters are
+  // cleared and joined back into st at the end, so that one class's launch
+  // tails overlap another's work.  The host enqueues in the same order.
+  int ncls = 0;
+  for (int c = 0; c < 3; ++c) ncls += g[c].k > 0 ? 1 : 0;
+  const bool forked = fork && !tm && ncls > 1;
+  hipStream_t cs[3] = {st, st, st};
+  if (forked) {
+    PAT_TRY(hipEventRecord(fork->ev[0], st));
+    int j = 0;
+    bool first = true;
     for (int c = 0; c < 3; ++c) {
       if (g[c].k == 0) continue;
-      const hipError_t e = dispatch_one_build<T, G>(op, stage, g[c].k, g[c].h, g[c].d, g[c].hp, g[c].in, g[c].out,
-                                                    g[c].ws, g[c].k == 1 ? nullptr : counters, 8 * c, st, tm);
-      if (e != hipSuccess) return e;
+      if (first) {
+        first = false;
+        continue;
+      }
+      cs[c] = fork->s[j++];
+      PAT_TRY(hipStreamWaitEvent(cs[c], fork->ev[0], 0));
     }
   }
-  return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (int stage = 1; stage <= 5 && e == hipSuccess; ++stage) {
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+      if (g[c].k == 0) continue;
+      e = dispatch_one_build<T, G>(op, stage, g[c].k, g[c].h, g[c].d, g[c].hp, g[c].in, g[c].out, g[c].ws,
+                                   g[c].k == 1 ? nullptr : counters, 8 * c, cs[c], tm);
+    }
+  }
+  if (forked) {
+    // (joined also after a failed launch: st then orders after everything
+    // that was enqueued)
+    int j = 1;
+    for (int c = 0; c < 3; ++c) {
+      if (cs[c] == st) continue;
+      const hipError_t r = hipEventRecord(fork->ev[j], cs[c]);
+      const hipError_t w = r == hipSuccess ? hipStreamWaitEvent(st, fork->ev[j], 0) : r;
+      if (e == hipSuccess) e = w;
+      ++j;
+    }
+  }
+  return e;
 }
 
 template <typename T, typename G>
@@ -3547,14 +3582,14 @@ hipError_t spread_only(const Inst& h, const Inst* dinst, const void* hpoly, cons
 
 hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* hpoly,
                   const void* const* in, void* const* out, void* const* ws, uint32_t* counters, hipStream_t stream,
-                  StageTimer* timer) {
+                  StageTimer* timer, const ForkStreams* fork) {
   switch (prec) {
     case PREC_F64:
-      return dispatch<double, cx<double>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
+      return dispatch<double, cx<double>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer, fork);
     case PREC_F32:
-      return dispatch<float, cx<float>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
+      return dispatch<float, cx<float>>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer, fork);
     case PREC_BF16:
-      return dispatch<float, bf2>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer);
+      return dispatch<float, bf2>(op, n, hinst, dinst, hpoly, in, out, ws, counters, stream, timer, fork);
   }
   return hipErrorInvalidValue;
 }

@@ -17,14 +17,24 @@ struct StageTimer {
   virtual ~StageTimer() {}
 };
 
+// Two extra streams and three events of one plan, for the batched launch:
+// its radix classes run on their own streams, forked from the caller's
+// stream and joined back into it.
+struct ForkStreams {
+  hipStream_t s[2] = {nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
 // One operator over n instances.  hinst: host copies of the descriptors,
 // dinst: their device addresses, hpoly: host copies of their tap-polynomial
 // tables.  in/out: user arrays; ws: per-instance workspace bases.  counters:
 // kNumCounters zeroed words of device memory for the persistent work queue,
 // or nullptr for one workgroup per work item.
+// fork: streams for the radix classes of a batch (nullptr, or with a timer
+// attached: everything on `stream`).
 hipError_t run_op(int prec, Op op, int n, const Inst* hinst, const Inst* const* dinst, const void* const* hpoly,
                   const void* const* in, void* const* out, void* const* ws, uint32_t* counters,
-                  hipStream_t stream, StageTimer* timer);
+                  hipStream_t stream, StageTimer* timer, const ForkStreams* fork = nullptr);
 
 // Stage a3 alone on user buffers (grid in, weighted node values out).
 hipError_t run_interp(int prec, const Inst& hinst, const Inst* dinst, const void* hpoly, const void* grid,

@@ -21,6 +21,7 @@ struct pat_plan {
   bool spread_ok = false;  // the spreading lists of a depth line fit in LDS (R^T, A)
   bool timing = false;
   void* timer = nullptr;   // owned by the ABI layer
+  void* fork = nullptr;    // streams of the batched calls led by this plan (ABI layer)
 };
 
 namespace pat {

@@ -370,6 +370,26 @@ def test_config5_batched_equals_single_calls(config5):
             assert np.array_equal(single, f)
 
 
+def test_batched_classes_join_the_callers_stream(config5):
+    """The radix classes of a batch run on streams of their own, forked from
+    the caller's stream and joined back into it.  Work that the caller
+    enqueues on its stream after the call (copies of the outputs, on a side
+    stream, with no device-wide wait in between) must see every class's
+    complete output, bit for bit the outputs of the first launch."""
+    cases, plans, ps, outs = config5
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fo = [torch.full((pl.n1, pl.n2, pl.nz), float("nan"), device="cuda") for pl in plans]
+        pat.reconstruct_batched(plans, ps, fo)
+        copies = [o.clone() for o in fo]
+        for o in fo:
+            o.fill_(float("nan"))
+    s.synchronize()
+    for plan, c, f in zip(plans, copies, outs):
+        assert np.array_equal(c.cpu().numpy(), f), plan.n1
+
+
 # ---------------------------------------------------------------------------
 # stage a3 alone
 
