@@ -356,9 +356,9 @@ __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* _
     lnbf = __builtin_ctz((unsigned)nbf);
     lnb = __builtin_ctz((unsigned)nb);
   }
-  // (one large-prime butterfly at a time: each has ILP of its own, and two
-  // in flight would double its register footprint)
-#pragma unroll(R >= 11 ? 1 : 0)
+  // (one butterfly per loop trip, not unrolled: each has ILP of its own, and
+  // two in flight would double the stage's register footprint)
+#pragma unroll 1
   for (int id = threadIdx.x; id < total; id += kBlock) {
     int b, bf;
     if constexpr (BF) {
@@ -1001,50 +1001,74 @@ __device__ __forceinline__ cx<T> taps_at(const cx<T>* U, int m, int j, const T* 
   return acc;
 }
 
+// The window of a node pair +nup, -nup with the paired taps: the node phase,
+// the first taps (reduced mod m) and both nodes' weights.  The two windows
+// are mirror images (the kernel is even and cK = TAPS/2 is an integer):
+// -nup's first tap is -(j0 + TAPS - 1) and its weights are +nup's reversed,
+// except for a node on a grid point (c nup an integer), where both offsets
+// are -1: the same weights, first tap -(j0 + TAPS - 2).  So the window
+// polynomials run once per pair, and lines with the same nodes share them.
+template <typename T, int TAPS>
+struct PairWin {
+  cx<T> ph;    // exp(-i pi nup) (1 on an uncentred grid)
+  int jp, jn;  // first taps of +nup and -nup, in [0, m)
+  T w[TAPS], wm[TAPS];
+};
+template <typename T, int TAPS, bool P2>
+__device__ __forceinline__ void pair_window(double nup, const Inst& I, const StageArgs& a, int m, double inv_m,
+                                            PairWin<T, TAPS>& pw) {
+  // (an uncentred grid, the interpolation-based methods, needs no node phase)
+  pw.ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
+  int j0;
+  const double d = tap_origin(I.c * nup, I.ck, &j0);
+  const T x = (T)(2.0 * d + 1.0);
+  const bool ongrid = d == -1.0;
+  tap_weights_pairs<T, TAPS>(a, x, pw.w);
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t) pw.wm[t] = bitsel(ongrid, pw.w[t], pw.w[TAPS - 1 - t]);
+  const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
+  pw.jp = wrap_tap<P2>(j0, m, inv_m);
+  pw.jn = wrap_tap<P2>(jm, m, inv_m);
+}
+// exp(-+i pi nup) sum_t phi(...) U[...] at +nup and -nup on one grid line U
+// (m points, with a halo of TAPS - 1 when HALO)
+template <typename T, int TAPS, bool HALO>
+__device__ __forceinline__ void pair_values(const cx<T>* U, int m, const PairWin<T, TAPS>& pw, cx<T>* vp,
+                                            cx<T>* vn) {
+  cx<T> sp, sn;
+  if (HALO || (pw.jp <= m - TAPS && pw.jn <= m - TAPS)) {
+    // both windows in one loop: two independent sums, two reads in flight
+    const cx<T>* up = U + pw.jp;
+    const cx<T>* un = U + pw.jn;
+    sp = sn = mk(T(0), T(0));
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      const cx<T> g = up[t], h = un[t];
+      sp.x += pw.w[t] * g.x;
+      sp.y += pw.w[t] * g.y;
+      sn.x += pw.wm[t] * h.x;
+      sn.y += pw.wm[t] * h.y;
+    }
+  } else {
+    sp = taps_at<T, TAPS, HALO>(U, m, pw.jp, pw.w);
+    sn = taps_at<T, TAPS, HALO>(U, m, pw.jn, pw.wm);
+  }
+  *vp = cmul(sp, pw.ph);
+  *vn = cmul(sn, cconj(pw.ph));
+}
+
 // The type-2 values at the node pair +nup and -nup:
 // exp(-+i pi nup) sum_t phi(...) U[...]; the two phases are conjugate.  With
-// the paired taps the two windows are mirror images (the kernel is even and
-// cK = TAPS/2 is an integer): -nup's first tap is -(j0 + TAPS - 1) and its
-// weights are +nup's reversed, except for a node on a grid point (c nup an
-// integer), where both offsets are -1: the same weights, first tap
-// -(j0 + TAPS - 2).  So the window polynomials run once per pair.
+// the paired taps by the mirrored windows of pair_window.
 template <typename T, int TAPS, bool PAIRS, bool P2, bool HALO = true>
 __device__ __forceinline__ void interp_pair(const cx<T>* U, int m, double inv_m, double nup, const Inst& I,
                                             const StageArgs& a, cx<T>* vp, cx<T>* vn) {
-  // (an uncentred grid, the interpolation-based methods, needs no node phase)
-  const cx<T> ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
   if constexpr (PAIRS) {
-    int j0;
-    const double d = tap_origin(I.c * nup, I.ck, &j0);
-    const T x = (T)(2.0 * d + 1.0);
-    const bool ongrid = d == -1.0;
-    T w[TAPS], wm[TAPS];
-    tap_weights_pairs<T, TAPS>(a, x, w);
-#pragma unroll
-    for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
-    const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
-    const int jp = wrap_tap<P2>(j0, m, inv_m), jn = wrap_tap<P2>(jm, m, inv_m);
-    cx<T> sp, sn;
-    if (HALO || (jp <= m - TAPS && jn <= m - TAPS)) {
-      // both windows in one loop: two independent sums, two reads in flight
-      const cx<T>* up = U + jp;
-      const cx<T>* un = U + jn;
-      sp = sn = mk(T(0), T(0));
-#pragma unroll
-      for (int t = 0; t < TAPS; ++t) {
-        const cx<T> g = up[t], h = un[t];
-        sp.x += w[t] * g.x;
-        sp.y += w[t] * g.y;
-        sn.x += wm[t] * h.x;
-        sn.y += wm[t] * h.y;
-      }
-    } else {
-      sp = taps_at<T, TAPS, HALO>(U, m, jp, w);
-      sn = taps_at<T, TAPS, HALO>(U, m, jn, wm);
-    }
-    *vp = cmul(sp, ph);
-    *vn = cmul(sn, cconj(ph));
+    PairWin<T, TAPS> pw;
+    pair_window<T, TAPS, P2>(nup, I, a, m, inv_m, pw);
+    pair_values<T, TAPS, HALO>(U, m, pw, vp, vn);
   } else {
+    const cx<T> ph = I.centred ? phase_mpi<T>(nup) : mk(T(1), T(0));
     *vp = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, nup, I, a), ph);
     *vn = cmul(tap_sum<T, TAPS, PAIRS, P2, HALO>(U, m, inv_m, -nup, I, a), cconj(ph));
   }
@@ -1056,6 +1080,20 @@ __device__ __forceinline__ double line_ak(const Inst& I, int line) {
   divmod<P2>(line, I.n2, &k1, &k2i);
   const int k2 = 2 * k2i < I.n2 ? k2i : k2i - I.n2;
   return I.a1 * (double)k1 * (double)k1 + I.a2 * (double)k2 * (double)k2;
+}
+
+// Lines taken in mirror pairs (3D): line slots 2P and 2P + 1 hold (k1, k2)
+// and (k1, -k2) of pair P = k1 (n2/2) + r with k2 = r, r = 1 .. n2/2 - 1,
+// and r = 0 gives the lines k2 = 0 and k2 = -n2/2.  The two lines of a pair
+// with r > 0 have the same |K_x|, so the same nodes and weights (*shared).
+template <bool P2>
+__device__ __forceinline__ int mirror_line(const Inst& I, int slot, bool* shared) {
+  const int h2 = I.n2 >> 1;
+  int k1, r;
+  divmod<P2>(slot >> 1, h2, &k1, &r);
+  *shared = r != 0;
+  const int k2 = (slot & 1) ? (r ? I.n2 - r : h2) : r;
+  return k1 * I.n2 + k2;
 }
 
 // a3 over a group of nl lines whose grids sit in LDS in natural order at
@@ -1600,7 +1638,7 @@ __device__ __forceinline__ int find_inst(const StageArgs& a, int item) {
     const int item_ = next_item(a, iter_);                                \
     if (item_ >= (a).total) break;                                        \
     const int inst_ = __builtin_amdgcn_readfirstlane(find_inst(a, item_)); \
-    const bool new_inst_ = inst_ != prev_inst_;                           \
+    [[maybe_unused]] const bool new_inst_ = inst_ != prev_inst_;          \
     prev_inst_ = inst_;                                                   \
     const Inst& I = *(a).inst[inst_];                                     \
     const int li = item_ - (a).off[inst_];
@@ -1690,7 +1728,7 @@ __device__ __forceinline__ void cut_pair(const Inst& I, const T* ws, int b2, int
 
 template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
-  constexpr bool P2 = RS == 0;
+  [[maybe_unused]] constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n1;
@@ -1779,7 +1817,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x1_r2c(StageArgs a) {
 
 template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
-  constexpr bool P2 = RS == 0;
+  [[maybe_unused]] constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n2;
@@ -1930,7 +1968,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
 
 template <typename T, int RS, int LL>
 __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArgs a) {
-  constexpr bool P2 = RS == 0;
+  [[maybe_unused]] constexpr bool P2 = RS == 0;
   const Inst& I = *a.inst[0];
   const int L = LL > 0 ? 1 << LL : I.n1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
@@ -2053,7 +2091,7 @@ __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArg
 // taking the real part of the full inverse DFT does.
 template <typename T, int RS>
 __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
-  constexpr bool P2 = RS == 0;
+  [[maybe_unused]] constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = tw + I.n1;
@@ -2302,7 +2340,7 @@ __device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int 
 
 template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
-  constexpr bool P2 = RS == 0;
+  [[maybe_unused]] constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
   // the twiddle table in LDS before the lines, or (long lines) read from memory
   cx<T>* lds = reinterpret_cast<cx<T>*>(pat_smem);
@@ -2768,6 +2806,174 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       if (b >= nl) return;
       cx<T>* o = out + b * nz;
+      const int k0 = PZ::natural(blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[k0 + r * stepz] = cconj(v[r]);
+    });
+    __syncthreads();
+  }
+}
+
+// k_line_nufft2_pipe_c for R on 3D plans whose depth lines are a quarter of
+// the grid lines (nz = m/4, m = 2^LM): a work item holds NL = 4096/m lines,
+// taken in mirror pairs (mirror_line), in 4096 padded points of LDS (34 KB,
+// four workgroups per CU).  Each of the 256 threads runs two first-stage
+// butterflies, and in the interpolation one node pair of one mirror pair:
+// its window, phase and weight serve both lines (the two lines of a pair
+// with r = 0 form their own).  The last grid-FFT stage works in place: every
+// thread reads its butterflies' 16 points, and after a barrier writes them
+// in natural order over the scratch; the interpolation outputs wait in
+// registers for a barrier and then overwrite the grid as the depth lines.
+template <int TAPS, int LM, int LZ>
+__global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
+  using T = float;
+  const Inst& I = *a.inst[0];
+  constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, NL = 4096 / m, half = nz / 2;
+  using PM = P2Plan<LM, p2_l16_m(LM)>;
+  using PZ = P2Plan<LZ, p2_l16_z(LZ)>;
+  static_assert(LZ == LM - 2 && (NL / 2) * half == kBlock, "one node pair of one mirror pair per thread");
+  static_assert(PM::rad(0) == 8 && PM::nst >= 2, "pipelined first stage");
+  constexpr int PADL = 4;
+  constexpr int LS = m + (m >> PADL);  // line stride in LDS
+  auto pad = [](int i) { return i + (i >> PADL); };
+  constexpr int sub = m >> 3, lsub = LM - 3;
+  constexpr int LPP = kBlock / sub;  // lines of one pass of first-stage butterflies (NL / 2)
+  const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
+  const T* sn = static_cast<const T*>(I.sn);
+  const int q = nt >> 2;
+  // inputs r = 0, 1, 6, 7 of a butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
+  // (formed where used: nothing per thread is held across the item loop that
+  // can be recomputed)
+  auto ns = [&](int i) { return j + (i == 0 ? 2 * q : i == 1 ? 3 * q : i == 2 ? 0 : q); };
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
+  cx<T>* outb = static_cast<cx<T>*>(a.out[0]);
+  const int lines = I.lines;
+  cx<T> pre[2][4];
+  auto fetch = [&](int item) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int slot = item * NL + bb + u * LPP;
+      const bool ok = slot < lines;
+      bool sh;
+      const cx<T>* gin = in + (size_t)(ok ? mirror_line<true>(I, slot, &sh) : 0) * nt;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pre[u][i] = ok ? gin[ns(i)] : mk(T(0), T(0));
+    }
+  };
+  constexpr int RL = PM::rad(PM::nst - 1), LRL = RL == 16 ? 4 : RL == 8 ? 3 : RL == 4 ? 2 : 1;
+  constexpr int NB = 16 / RL;  // last-stage butterflies per thread
+  constexpr int step = m / RL;
+  constexpr int stepz = nz / PZ::rad(PZ::nst - 1);
+  const double wsc = I.wcoef * I.scale;
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+    const int line0 = item * NL;
+    const int nl = min(NL, lines - line0);
+    // (the deconvolution factors and the first twiddle are read per item, not
+    // held across it: the registers go to the later phases)
+    T snr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) snr[i] = sn[ns(i)];
+    const cx<T> w1 = twm[j];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      cx<T> v[8];
+      v[0] = cscl(pre[u][0], snr[0]);
+      v[1] = cscl(pre[u][1], snr[1]);
+      v[2] = v[3] = v[4] = v[5] = mk(T(0), T(0));
+      v[6] = cscl(pre[u][2], snr[2]);
+      v[7] = cscl(pre[u][3], snr[3]);
+      dft_pow2<T, 8>(v);
+      twiddle_pow2<T, 8>(v, w1);
+      const int b = bb + u * LPP;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[pad(b * m + j + r * sub)] = v[r];
+    }
+    __syncthreads();
+    p2_stages<T, LM, 1, p2_l16_m(LM), PADL>(buf, twm, NL);
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    {
+      // last grid stage, in place: read, barrier, write in natural order
+      // (line b at buf + b LS, unpadded within its line)
+      cx<T> lv[NB][RL];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int id = (int)threadIdx.x + u * kBlock;
+        const int b = id >> (LM - LRL), blk = id & ((m >> LRL) - 1);
+        const cx<T>* p = buf + pad(b * m + blk * RL);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) lv[u][r] = p[r];
+        dft_pow2<T, RL>(lv[u]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int id = (int)threadIdx.x + u * kBlock;
+        const int b = id >> (LM - LRL), blk = id & ((m >> LRL) - 1);
+        cx<T>* g = buf + b * LS;
+        const int k0 = PM::natural(blk * RL);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) g[k0 + r * step] = lv[u][r];
+      }
+    }
+    __syncthreads();
+    {
+      // interpolation (R: |l| = 1 .. nz/2, node pairs +-nu+): node pair p of
+      // mirror pair h
+      const int h = (int)threadIdx.x >> (LZ - 1), la = ((int)threadIdx.x & (half - 1)) + 1;
+      const bool act = 2 * h < nl;
+      cx<T> o[4] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+      if (act) {
+        bool sh, sh1;
+        const int L0 = mirror_line<true>(I, line0 + 2 * h, &sh);
+        const int L1 = mirror_line<true>(I, line0 + 2 * h + 1, &sh1);
+        const double bl = I.b * (double)la * (double)la;
+        double nup = sqrt_nt(line_ak<true>(I, L0) + bl);
+        PairWin<T, TAPS> pw;
+        pair_window<T, TAPS, true>(nup, I, a, m, 0.0, pw);
+        double wl = wsc * (double)la * rcp_nt(nup);
+        cx<T> vp, vn;
+        pair_values<T, TAPS, false>(buf + 2 * h * LS, m, pw, &vp, &vn);
+        if (la < half) {
+          o[0] = cscl(vp, T(wl));
+          o[1] = cscl(vn, T(wl));
+        } else {
+          o[0] = cscl(cadd(vp, vn), T(0.5 * wl));
+        }
+        if (!sh) {
+          nup = sqrt_nt(line_ak<true>(I, L1) + bl);
+          pair_window<T, TAPS, true>(nup, I, a, m, 0.0, pw);
+          wl = wsc * (double)la * rcp_nt(nup);
+        }
+        pair_values<T, TAPS, false>(buf + (2 * h + 1) * LS, m, pw, &vp, &vn);
+        if (la < half) {
+          o[2] = cscl(vp, T(wl));
+          o[3] = cscl(vn, T(wl));
+        } else {
+          o[2] = cscl(cadd(vp, vn), T(0.5 * wl));
+        }
+      }
+      __syncthreads();
+      // the depth lines over the grid: line b at b nz (padded); the Nyquist
+      // lane also writes l = 0 (weight 0)
+      const int e0 = 2 * h * nz, e1 = e0 + nz;
+      const int lp = la < half ? la : half, ln = la < half ? nz - la : 0;
+      buf[pad(e0 + lp)] = cconj(o[0]);
+      buf[pad(e0 + ln)] = cconj(o[1]);
+      buf[pad(e1 + lp)] = cconj(o[2]);
+      buf[pad(e1 + ln)] = cconj(o[3]);
+    }
+    __syncthreads();
+    p2_stages<T, LZ, 0, p2_l16_z(LZ), PADL>(buf, twz, NL);
+    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true, PADL>(buf, nz, NL, nz, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      if (b >= nl) return;
+      bool sh;
+      cx<T>* o = outb + (size_t)mirror_line<true>(I, line0 + b, &sh) * nz;
       const int k0 = PZ::natural(blk * R);
 #pragma unroll
       for (int r = 0; r < R; ++r) o[k0 + r * stepz] = cconj(v[r]);
@@ -3283,6 +3489,21 @@ struct Runner {
     StageArgs a = base(IT_LF, true, mode, in, out);
     if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
       const Inst& I = h[0];
+      if (n == 1 && !a.counter && a.pair_ok && mode == 0 && I.m == 2 * I.nt && 4 * I.nz == I.m && I.n2 >= 4 &&
+          I.fm.nst >= 2 && I.fm.rad[0] == 8) {
+        // R on 3D plans with nz = m/4: line groups in mirror pairs, m = 2^8 .. 2^11
+        const int lm = __builtin_ctz((unsigned)I.m);
+        if (lm >= 8 && lm <= 11) {
+          a.total = cdiv(I.lines, 4096 / I.m);
+          a.off[1] = a.total;
+          const size_t shm = (size_t)4096 * 17 / 16 * cs;
+          auto go = [&](auto kern) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm); };
+          if (lm == 8) return go(k_line_nufft2_mirror<TAPS, 8, 6>);
+          if (lm == 9) return go(k_line_nufft2_mirror<TAPS, 9, 7>);
+          if (lm == 10) return go(k_line_nufft2_mirror<TAPS, 10, 8>);
+          return go(k_line_nufft2_mirror<TAPS, 11, 9>);
+        }
+      }
       if (n == 1 && !a.counter && a.pair_ok && I.m == 2 * I.nt && I.m >= I.nz && I.fm.nst >= 2 &&
           I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock) {
         // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2 (with
