@@ -396,7 +396,8 @@ def oracle_parity(p_np, g, outputs, keep, np):
 
 KERNEL_OF_STAGE = {
     # library stage name -> kernel symbol prefixes in the profiler's output
-    "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<", "void pat::k_line_nufft2_pipe_c<"),
+    "nufft_fused": ("void pat::k_line_nufft2<", "void pat::k_line_nufft2_pipe<", "void pat::k_line_nufft2_pipe_c<",
+                    "void pat::k_line_nufft2_mirror<"),
     "nufft_adjoint_fused": ("void pat::k_line_nufft1<", "void pat::k_line_nufft1_c<", "void pat::k_line_nufft1_w<"),
     "dft_x1": ("void pat::k_tr_x1_r2c<", "void pat::k_tr_x1_pipe<"),
     "dft_x2": ("void pat::k_tr_x2<", "void pat::k_tr_x2_pipe<"),
