@@ -485,6 +485,20 @@ __device__ __forceinline__ int dif_natural_p2(const FftDesc& d, int pos) {
   return k;
 }
 
+// The inverse of dif_natural_p2: the position of natural index k in the
+// in-place DIF output (its digits, least significant first, become the
+// position's digits, most significant first).
+__device__ __forceinline__ int dif_position_p2(const FftDesc& d, int k) {
+  int pos = 0, lspan = __builtin_ctz((unsigned)d.L);
+  for (int s = 0; s < d.nst; ++s) {
+    const int lr = __builtin_ctz((unsigned)d.rad[s]);
+    lspan -= lr;
+    pos += (k & (d.rad[s] - 1)) << lspan;
+    k >>= lr;
+  }
+  return pos;
+}
+
 // The last stage (sub = 1, no twiddles) of a power-of-two DIF transform,
 // handing each butterfly's R outputs (positions blk*R + r) to
 // sink(b, blk, v) instead of writing them back.
@@ -2299,11 +2313,16 @@ template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
-  // the twiddle table in LDS before the lines, or (long lines) read from memory
+  // the twiddle table in LDS before the lines, or read from memory: for
+  // long lines, and for power-of-two lengths (their workgroups, one item
+  // each, copy the table slower than the FFT reads it from cache; the LDS
+  // region stays reserved, which holds the kernel to fewer workgroups per
+  // CU: freeing it made the kernel 1.5x slower)
   cx<T>* lds = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = I.twg_m ? lds : lds + I.m;
-  const cx<T>* tw = I.twg_m ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
-  if (new_inst_ && !I.twg_m) load_twiddles(lds, I, I.fm);
+  const bool twg = P2 || I.twg_m;
+  const cx<T>* tw = twg ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
+  if (new_inst_ && !twg) load_twiddles(lds, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
@@ -2315,7 +2334,9 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   for (int e = threadIdx.x; e < nl * m; e += kBlock) {
     int b, j;
     divmod<P2>(e, m, &b, &j);
-    GridIO<T, G>::st(grid, (size_t)line0 * m + e, buf[b * m + perm[j]]);
+    // (power-of-two lengths: the DIF position from the index, no table)
+    const int pos = P2 ? dif_position_p2(I.fm, j) : perm[j];
+    GridIO<T, G>::st(grid, (size_t)line0 * m + e, buf[b * m + pos]);
   }
   PAT_END_ITEM
 }
@@ -2332,21 +2353,25 @@ __device__ __forceinline__ void ifft_pick_deconv(const Inst& I, cx<T>* buf, int 
   for (int e = threadIdx.x; e < nl * nt; e += kBlock) {
     int b, n;
     divmod<P2>(e, nt, &b, &n);
-    int pos = n - nt / 2;
-    if (pos < 0) pos += m;
-    x[e] = cscl(cconj(buf[b * m + perm[pos]]), sn[n]);
+    int k = n - nt / 2;
+    if (k < 0) k += m;
+    // (power-of-two lengths: the DIF position from the index, no table)
+    const int pos = P2 ? dif_position_p2(I.fm, k) : perm[k];
+    x[e] = cscl(cconj(buf[b * m + pos]), sn[n]);
   }
 }
 
 template <typename T, typename G, int RS>
 __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
-  [[maybe_unused]] constexpr bool P2 = RS == 0;
+  constexpr bool P2 = RS == 0;
   PAT_FOR_EACH_ITEM(a)
-  // the twiddle table in LDS before the lines, or (long lines) read from memory
+  // the twiddle table in LDS before the lines, or read from memory (long
+  // lines, power-of-two lengths: see k_line_a2)
   cx<T>* lds = reinterpret_cast<cx<T>*>(pat_smem);
   cx<T>* buf = I.twg_m ? lds : lds + I.m;
-  const cx<T>* tw = I.twg_m ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
-  if (new_inst_ && !I.twg_m) load_twiddles(lds, I, I.fm);
+  const bool twg = P2 || I.twg_m;
+  const cx<T>* tw = twg ? static_cast<const cx<T>*>(I.tw) + I.fm.tw : lds;
+  if (new_inst_ && !twg) load_twiddles(lds, I, I.fm);
   const int m = I.m, nt = I.nt;
   const int line0 = li * I.lpw_m;
   const int nl = min(I.lpw_m, I.lines - line0);
