@@ -2341,6 +2341,79 @@ __global__ __launch_bounds__(kBlock) void k_line_a2(StageArgs a) {
   PAT_END_ITEM
 }
 
+// Stage a2 alone (the staged and bf16-grid paths) as a software pipeline for
+// one FP32 instance with the centred c = 2 grid and m = 2^LM points, the
+// first half of k_line_nufft2_pipe_c: a persistent grid strides over line
+// groups of 2048/m lines; each workgroup's first FFT stage takes the four
+// nonzero samples per butterfly from registers loaded during the previous
+// group, the radix plan is compile-time, the last stage writes natural
+// order into an LDS buffer, and the grid lines leave it in coalesced stores.
+template <typename G, int LM>
+__global__ __launch_bounds__(kBlock, 4) void k_line_a2_pipe(StageArgs a) {
+  using T = float;
+  const Inst& I = *a.inst[0];
+  constexpr int m = 1 << LM, nt = m / 2, lpw = 2048 / m;
+  using PM = P2Plan<LM, p2_l16_m(LM)>;
+  static_assert(PM::rad(0) == 8 && PM::nst >= 2, "pipelined first stage");
+  constexpr int PADL = 4;
+  auto pad = [](int i) { return i + (i >> PADL); };
+  constexpr int sub = m >> 3, lsub = LM - 3;
+  const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  cx<T>* gn = reinterpret_cast<cx<T>*>(pat_smem);  // grid lines, natural order
+  cx<T>* gp = gn + lpw * m;                          // FFT scratch, padded
+  const T* sn = static_cast<const T*>(I.sn);
+  const int q = nt >> 2;
+  // inputs r = 0, 1, 6, 7 of the butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
+  const int ns[4] = {j + 2 * q, j + 3 * q, j, j + q};
+  T snr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) snr[i] = sn[ns[i]];
+  const cx<T> w1 = twm[j];
+  const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
+  G* grid = static_cast<G*>(a.out[0]);
+  cx<T> pre[4];
+  auto fetch = [&](int item) {
+    const int line = item * lpw + bb;
+    const bool ok = line < I.lines;
+    const cx<T>* gin = in + (size_t)line * nt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pre[i] = ok ? gin[ns[i]] : mk(T(0), T(0));
+  };
+  constexpr int step = m / PM::rad(PM::nst - 1);
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+    const int line0 = item * lpw;
+    const int nl = min(lpw, I.lines - line0);
+    {
+      cx<T> v[8];
+      v[0] = cscl(pre[0], snr[0]);
+      v[1] = cscl(pre[1], snr[1]);
+      v[2] = v[3] = v[4] = v[5] = mk(T(0), T(0));
+      v[6] = cscl(pre[2], snr[2]);
+      v[7] = cscl(pre[3], snr[3]);
+      dft_pow2<T, 8>(v);
+      twiddle_pow2<T, 8>(v, w1);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) gp[pad(bb * m + j + r * sub)] = v[r];
+    }
+    __syncthreads();
+    p2_stages<T, LM, 1, p2_l16_m(LM), PADL>(gp, twm, lpw);
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true, PADL>(gp, m, lpw, m, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      cx<T>* g = gn + b * m;
+      const int k0 = PM::natural(blk * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) g[k0 + r * step] = v[r];
+    });
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl * m; e += kBlock) GridIO<T, G>::st(grid, (size_t)line0 * m + e, gn[e]);
+    __syncthreads();
+  }
+}
+
 // transpose of a2 on LDS grids (natural order, conjugated on entry by the
 // caller): X_n = s_n (inverse DFT of the grid line)[(n - nt/2) mod m]
 template <typename T, int RS>
@@ -3468,6 +3541,20 @@ struct Runner {
   }
   hipError_t a2(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
+    if constexpr (sizeof(T) == 4 && P2) {
+      // one instance, centred c = 2 grid, m = 2^8 .. 2^11: the pipelined kernel
+      const Inst& I = h[0];
+      const int lm = __builtin_ctz((unsigned)I.m);
+      if (n == 1 && !a.counter && I.centred && I.m == 2 * I.nt && lm >= 8 && lm <= 11 && I.fm.rad[0] == 8 &&
+          I.lpw_m == 2048 / I.m) {
+        const size_t shm = (size_t)(2048 + 2048 + 2048 / 16) * cs;
+        auto go = [&](auto kern) { return launch_persistent(kern, "deconv_pad_fft", a, shm, st, tm); };
+        if (lm == 8) return go(k_line_a2_pipe<G, 8>);
+        if (lm == 9) return go(k_line_a2_pipe<G, 9>);
+        if (lm == 10) return go(k_line_a2_pipe<G, 10>);
+        return go(k_line_a2_pipe<G, 11>);
+      }
+    }
     return launch(k_line_a2<T, G, RS>, "deconv_pad_fft", a, max_over([](const Inst& I) { return lds_line_m(I, cs); }),
                   st, tm);
   }
