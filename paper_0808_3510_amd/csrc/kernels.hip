@@ -2457,6 +2457,63 @@ __global__ __launch_bounds__(kBlock) void k_line_a2t(StageArgs a) {
   PAT_END_ITEM
 }
 
+// The transpose of a2 alone (the staged paths of R^T and A) as a software
+// pipeline for one FP32 instance with the centred c = 2 grid and m = 2^LM
+// points: a persistent grid strides over line groups of 2048/m lines; each
+// workgroup stores its group's grid lines (conjugated) into a padded LDS
+// scratch, issues the loads of the next group into registers, runs the
+// compile-time FFT, and its last stage writes the picked, deconvolved time
+// samples X_n = s_n conj(G_k), k = (n - nt/2) mod m, straight to memory.
+template <typename G, int LM>
+__global__ __launch_bounds__(kBlock, 4) void k_line_a2t_pipe(StageArgs a) {
+  using T = float;
+  const Inst& I = *a.inst[0];
+  constexpr int m = 1 << LM, nt = m / 2, lpw = 2048 / m, per = 2048 / kBlock;
+  using PM = P2Plan<LM, p2_l16_m(LM)>;
+  static_assert(PM::nst >= 2, "two or more stages");
+  constexpr int PADL = 4;
+  auto pad = [](int i) { return i + (i >> PADL); };
+  cx<T>* gp = reinterpret_cast<cx<T>*>(pat_smem);
+  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+  const T* sn = static_cast<const T*>(I.sn);
+  const G* grid = static_cast<const G*>(a.in[0]);
+  cx<T>* xout = static_cast<cx<T>*>(a.out[0]);
+  const size_t npts = (size_t)I.lines * m;
+  cx<T> pre[per];
+  auto fetch = [&](int item) {
+    const size_t base = (size_t)item * lpw * m;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const size_t e = base + threadIdx.x + u * kBlock;
+      pre[u] = e < npts ? GridIO<T, G>::ld(grid, e) : mk(T(0), T(0));
+    }
+  };
+  constexpr int step = m / PM::rad(PM::nst - 1);
+  int item = blockIdx.x;
+  if (item < a.total) fetch(item);
+  for (; item < a.total; item += gridDim.x) {
+    const int line0 = item * lpw;
+    const int nl = min(lpw, I.lines - line0);
+#pragma unroll
+    for (int u = 0; u < per; ++u) gp[pad((int)threadIdx.x + u * kBlock)] = cconj(pre[u]);
+    __syncthreads();
+    if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
+    p2_stages<T, LM, 0, p2_l16_m(LM), PADL>(gp, twm, lpw);
+    fft_last_stage_p2<T, PM::rad(PM::nst - 1), true, PADL>(gp, m, lpw, m, 1, [&](int b, int blk, const auto& v) {
+      constexpr int R = sizeof(v) / sizeof(v[0]);
+      if (b >= nl) return;
+      const int k0 = PM::natural(blk * R);
+      cx<T>* x = xout + (size_t)(line0 + b) * nt;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n = (k0 + r * step + nt / 2) & (m - 1);
+        if (n < nt) x[n] = cscl(cconj(v[r]), sn[n]);
+      }
+    });
+    __syncthreads();
+  }
+}
+
 // Four consecutive grid cells to memory (p 16-byte aligned for the vector
 // forms; bf16 falls back to single cells otherwise).
 template <typename T, typename G>
@@ -3560,6 +3617,19 @@ struct Runner {
   }
   hipError_t a2t(const void* const* in, void* const* out) {
     StageArgs a = base(IT_LM, false, 0, in, out);
+    if constexpr (sizeof(T) == 4 && P2) {
+      // one instance, centred c = 2 grid, m = 2^8 .. 2^11: the pipelined kernel
+      const Inst& I = h[0];
+      const int lm = __builtin_ctz((unsigned)I.m);
+      if (n == 1 && !a.counter && I.centred && I.m == 2 * I.nt && lm >= 8 && lm <= 11 && I.lpw_m == 2048 / I.m) {
+        const size_t shm = (size_t)(2048 + 2048 / 16) * cs;
+        auto go = [&](auto kern) { return launch_persistent(kern, "ifft_pick_deconv", a, shm, st, tm); };
+        if (lm == 8) return go(k_line_a2t_pipe<G, 8>);
+        if (lm == 9) return go(k_line_a2t_pipe<G, 9>);
+        if (lm == 10) return go(k_line_a2t_pipe<G, 10>);
+        return go(k_line_a2t_pipe<G, 11>);
+      }
+    }
     return launch(k_line_a2t<T, G, RS>, "ifft_pick_deconv", a,
                   max_over([](const Inst& I) { return lds_line_m(I, cs); }), st, tm);
   }
