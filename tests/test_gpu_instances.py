@@ -98,3 +98,30 @@ def test_instance_single_planes(lm, lz, op):
             assert np.abs(got).max() <= TOL * np.abs(full).max()
         else:
             check(got, exp, name)
+
+
+# The staged path (grid stored between stages; the bf16-grid option always
+# runs it) has compile-time pipelines of its own for one FP32 instance with
+# the c = 2 grid and m = 2^8 .. 2^11: the grid FFT of R and A^T
+# (k_line_a2_pipe) and its transpose in R^T and A (k_line_a2t_pipe).  Every
+# size against the oracle, FP32 and bf16 grid storage (8 mantissa bits).
+STAGED_TOL = {"f32": TOL, "bf16grid": 1e-2}
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("prec", ["f32", "bf16grid"])
+@pytest.mark.parametrize("lm", [8, 9, 10, 11])
+def test_staged_pipelines_match_oracle(lm, prec, op):
+    g = geo(lm, lm - 2, 4)
+    print(f"staged m=2^{lm} {prec} {op} {g}", flush=True)
+    n_in = g["nt"] if op in ("reconstruct", "forward_adjoint") else g["nz"]
+    x = inputs.random_array(shape(g, n_in), 970 + lm)
+    plan = pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], precision=prec,
+                    device=DEV)
+    plan.set_fused(False)
+    got = run(plan, op, x)
+    exp = getattr(recon, op)(x, g)
+    rel = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    mx = np.abs(got - exp).max() / np.abs(exp).max()
+    print(f"  relL2 {rel:.2e}, max {mx:.2e}", flush=True)
+    assert rel <= STAGED_TOL[prec] and mx <= STAGED_TOL[prec], (rel, mx)
