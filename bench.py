@@ -63,8 +63,8 @@ def stage_flops(name, n1, n2, nt, nz, m, taps=12):
     """Algorithmic flops of one launch of the fused NUFFT stages, per line:
     deconvolution (2 nt), the oversampled FFT (5 m log2 m), per node the tap
     weights by the fitted even/odd polynomials (17 flops per tap pair plus
-    one square, the cheapest evaluation of the window transform this build
-    has), taps complex-by-real multiply-adds (4 each), phase and weight (8),
+    one square, the cheapest evaluation of the window transform the
+    library has), taps complex-by-real multiply-adds (4 each), phase and weight (8),
     and the depth FFT (5 nz log2 nz).  None for other stages."""
     if name not in ("nufft_fused", "nufft_adjoint_fused"):
         return None
