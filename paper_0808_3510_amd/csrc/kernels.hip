@@ -2883,8 +2883,9 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft2_pipe(StageArgs a) {
 // stages, their loops and the output positions fixed by P2Plan.  Bounded at
 // four waves per SIMD (128 registers): a five-wave cap (96) made several
 // instances spill, while those that need no more than 96 still run five.
+// In FP64 (twice the registers and LDS) at two.
 template <typename T, int TAPS, int LM, int LZ>
-__global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_pipe_c(StageArgs a) {
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft2_pipe_c(StageArgs a) {
   const Inst& I = *a.inst[0];
   constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, lpw = 2048 / m;
   using PM = P2Plan<LM, p2_l16_m(LM)>;
@@ -3686,6 +3687,10 @@ struct Runner {
           return go(k_line_nufft2_mirror<TAPS, 11, 9>);
         }
       }
+    }
+    if constexpr (P2 && TAPS > 0) {
+      // FP32, and FP64 at two waves per SIMD (its launch bound)
+      const Inst& I = h[0];
       if (n == 1 && !a.counter && a.pair_ok && I.m == 2 * I.nt && I.m >= I.nz && I.fm.nst >= 2 &&
           I.fm.rad[0] == 8 && (I.m / 8) * I.lpw_f == kBlock) {
         // compile-time sizes for m = 2^8 .. 2^11 and nz = m/4 or m/2 (with
@@ -3704,7 +3709,7 @@ struct Runner {
           if (lm == 10) return go(k_line_nufft2_pipe_c<T, TAPS, 10, 9>);
           if (lm == 11) return go(k_line_nufft2_pipe_c<T, TAPS, 11, 10>);
         }
-        return go(k_line_nufft2_pipe<T, TAPS>);
+        if constexpr (sizeof(T) == 4) return go(k_line_nufft2_pipe<T, TAPS>);
       }
     }
     return launch(k_line_nufft2<T, RS, TAPS>, "nufft_fused", a,

@@ -125,3 +125,24 @@ def test_staged_pipelines_match_oracle(lm, prec, op):
     mx = np.abs(got - exp).max() / np.abs(exp).max()
     print(f"  relL2 {rel:.2e}, max {mx:.2e}", flush=True)
     assert rel <= STAGED_TOL[prec] and mx <= STAGED_TOL[prec], (rel, mx)
+
+
+# FP64 runs the same compile-time type-2 kernel (k_line_nufft2_pipe_c at two
+# waves per SIMD) for R and A^T: every size against the oracle at 1e-9.
+@pytest.mark.parametrize("op", ["reconstruct", "forward_adjoint"])
+@pytest.mark.parametrize("n2", [1, 4])
+@pytest.mark.parametrize("lm,lz", INSTANCES)
+def test_instance_fp64_matches_oracle(lm, lz, n2, op):
+    g = geo(lm, lz, n2)
+    print(f"fp64 instance m=2^{lm} nz=2^{lz} {op} {g}", flush=True)
+    x = inputs.random_array(shape(g, g["nt"]), 990 + lm * 10 + lz)
+    plan = pat.Plan(g["n1"], g["n2"], g["nt"], g["nz"], g["dx"], g["dt"], g["dz"], g["vs"], precision="f64",
+                    device=DEV)
+    y = getattr(plan, op)(torch.from_numpy(np.ascontiguousarray(x)).to(DEV, torch.float64))
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    exp = getattr(recon, op)(x, g)
+    rel = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    mx = np.abs(got - exp).max() / np.abs(exp).max()
+    print(f"  relL2 {rel:.2e}, max {mx:.2e}", flush=True)
+    assert rel <= 1e-9 and mx <= 1e-9, (rel, mx)
