@@ -12,18 +12,28 @@
 //   k_tr_*_pipe   the three above as software pipelines (one FP32 instance)
 //   k_line_fft    DFT along contiguous lines (depth axis)
 //   k_line_a2     deconvolve by 1/Psi, centre, zero-pad to c*nt, FFT (eq. nufft-c)
+//                 (k_line_a2_pipe: its software pipeline, c = 2, sizes fixed
+//                 at compile time)
 //   k_line_a2t    its transpose: inverse FFT, pick, multiply by 1/Psi
+//                 (k_line_a2t_pipe: likewise)
 //   k_line_interp type-2 interpolation with 2cK Kaiser-Bessel taps (eq. nufft-a)
-//                 and the Jacobian weight (eq. fft-0)
+//                 and the Jacobian weight (eq. fft-0) (k_line_interp_stream:
+//                 persistent, the next line group streamed into registers)
 //   k_line_spread its transpose (type-1), gathered per grid cell over the
 //                 monotone node list of the line: no atomics, deterministic
+//                 (k_line_spread_w: one line per wavefront, segmented sums
+//                 across lanes, FP32)
 //   k_line_nufft2 a2 + a3 + inverse depth DFT fused per line group in LDS
 //                 (k_line_nufft2_pipe: its software pipeline for c = 2;
-//                 k_line_nufft2_pipe_c: the same for sizes fixed at compile time)
+//                 k_line_nufft2_pipe_c: the same for sizes fixed at compile
+//                 time; k_line_nufft2_mirror: R on 3D plans with nz = m/4,
+//                 four lines per item in mirror pairs sharing node windows)
 //   k_line_nufft1 depth DFT + spreading + transposed a2 fused per line in LDS
-//                 (k_line_nufft1_c: sizes fixed at compile time)
+//                 (k_line_nufft1_c: sizes fixed at compile time;
+//                 k_line_nufft1_w: one line per wavefront, FP32)
 // The fused kernels never store the oversampled grid; the staged ones do
-// (bf16 grid option, and the stand-alone a3 / spreading entry points).
+// (bf16 grid option, long grid lines, and the stand-alone a3 / spreading
+// entry points).
 //
 // Uniform FFTs are in-place decimation-in-frequency mixed-radix transforms in
 // LDS; bin k ends at position perm[k] (a table built by the host plan).  Two
