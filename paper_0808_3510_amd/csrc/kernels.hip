@@ -352,7 +352,8 @@ __device__ __forceinline__ void twiddle_pow2(cx<T>* v, cx<T> w1) {
 // spare slot after every 2^PADL points, so that the strided butterfly
 // accesses of the later stages (lanes 2^PADL points apart) spread over the
 // LDS banks (power-of-two radices only).
-template <typename T, int R, bool P2, bool BF, typename Ptr = cx<T>*, int PADL = 0>
+// (NT: the threads of the workgroup)
+template <typename T, int R, bool P2, bool BF, typename Ptr = cx<T>*, int PADL = 0, int NT = kBlock>
 __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* __restrict__ tw, int nb,
                                           int bs, int es) {
   static_assert(PADL == 0 || R == 2 || R == 4 || R == 8 || R == 16, "padded scratch: power-of-two radices");
@@ -369,7 +370,7 @@ __device__ __forceinline__ void fft_stage(Ptr buf, int Li, int L, const cx<T>* _
   // (one butterfly per loop trip, not unrolled: each has ILP of its own, and
   // two in flight would double the stage's register footprint)
 #pragma unroll 1
-  for (int id = threadIdx.x; id < total; id += kBlock) {
+  for (int id = threadIdx.x; id < total; id += NT) {
     int b, bf;
     if constexpr (BF) {
       if constexpr (P2) {
@@ -512,11 +513,11 @@ __device__ __forceinline__ int dif_position_p2(const FftDesc& d, int k) {
 // The last stage (sub = 1, no twiddles) of a power-of-two DIF transform,
 // handing each butterfly's R outputs (positions blk*R + r) to
 // sink(b, blk, v) instead of writing them back.
-template <typename T, int R, bool BF, int PADL = 0, typename Sink>
+template <typename T, int R, bool BF, int PADL = 0, int NT = kBlock, typename Sink>
 __device__ __forceinline__ void fft_last_stage_p2(const cx<T>* buf, int L, int nb, int bs, int es, Sink sink) {
   const int nbf = L / R;
   const int lnbf = __builtin_ctz((unsigned)nbf), lnb = __builtin_ctz((unsigned)nb);
-  for (int id = threadIdx.x; id < nbf * nb; id += kBlock) {
+  for (int id = threadIdx.x; id < nbf * nb; id += NT) {
     int b, blk;
     if constexpr (BF) {
       blk = id & (nbf - 1);
@@ -651,13 +652,13 @@ static_assert(P2Plan<10, true>::nst == 3 && P2Plan<10, true>::rad(1) == 8 && P2P
 // Stages S .. nst - 2 (twiddled, in place) of the compile-time plan of 2^E
 // points on nb lines of stride 2^E, one block barrier after each.
 // (PADL: the padded scratch of fft_stage.)
-template <typename T, int E, int S, bool L16 = false, int PADL = 0>
+template <typename T, int E, int S, bool L16 = false, int PADL = 0, int NT = kBlock>
 __device__ __forceinline__ void p2_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int nb) {
   using Pl = P2Plan<E, L16>;
   if constexpr (S + 1 < Pl::nst) {
-    fft_stage<T, Pl::rad(S), true, true, cx<T>*, PADL>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
+    fft_stage<T, Pl::rad(S), true, true, cx<T>*, PADL, NT>(buf, 1 << Pl::lspan(S), 1 << E, tw, nb, 1 << E, 1);
     __syncthreads();
-    p2_stages<T, E, S + 1, L16, PADL>(buf, tw, nb);
+    p2_stages<T, E, S + 1, L16, PADL, NT>(buf, tw, nb);
   }
 }
 
@@ -2990,25 +2991,71 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft2_
 // thread reads its butterflies' 16 points, and after a barrier writes them
 // in natural order over the scratch; the interpolation outputs wait in
 // registers for a barrier and then overwrite the grid as the depth lines.
-template <int TAPS, int LM, int LZ>
-__global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
+// Entries k < L / r of the twiddle table that the twiddled stages (all but
+// the last) of a compile-time plan read, r the smallest of their radices.
+template <typename Pl, int L>
+constexpr int twiddle_extent() {
+  int r = 16;
+  for (int s = 0; s + 1 < Pl::nst; ++s) r = Pl::rad(s) < r ? Pl::rad(s) : r;
+  return L / r;
+}
+// LDS of k_line_nufft2_mirror (FP32) with NT threads: its 16 NT padded
+// points, the twiddles of both FFTs' twiddled stages and, where the
+// workgroups of four waves per SIMD still fit in 160 KB, the deconvolution
+// factors s_n.
+template <int LM, int NT>
+struct MirrorLds {
+  static constexpr int m = 1 << LM, nt = m / 2, nz = m / 4, P = 16 * NT;
+  static constexpr int TWM = twiddle_extent<P2Plan<LM, p2_l16_m(LM)>, m>();
+  static constexpr int TWZ = twiddle_extent<P2Plan<LM - 2, p2_l16_z(LM - 2)>, nz>();
+  static constexpr int kPts = P + (P >> 4);
+  static constexpr int kTw = (TWM + TWZ) * 8, kSn = nt * 4;
+  static constexpr int kGroups = 16 * 64 / NT;  // workgroups per CU at four waves per SIMD
+  static constexpr bool SN = (kPts * 8 + kTw + kSn) * kGroups <= 160 * 1024;
+  static constexpr int bytes = kPts * 8 + kTw + (SN ? kSn : 0);
+};
+static_assert(MirrorLds<10, 256>::TWM == 128 && MirrorLds<10, 256>::TWZ == 64 && MirrorLds<10, 256>::SN &&
+                  !MirrorLds<11, 256>::SN && MirrorLds<11, 256>::bytes * 4 <= 160 * 1024 &&
+                  MirrorLds<10, 128>::bytes * 8 <= 160 * 1024,
+              "four waves per SIMD");
+
+template <int TAPS, int LM, int LZ, int NT>
+__global__ __launch_bounds__(NT, 4) void k_line_nufft2_mirror(StageArgs a) {
   using T = float;
   const Inst& I = *a.inst[0];
-  constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, NL = 4096 / m, half = nz / 2;
+  constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, NL = 16 * NT / m, half = nz / 2;
   using PM = P2Plan<LM, p2_l16_m(LM)>;
   using PZ = P2Plan<LZ, p2_l16_z(LZ)>;
-  static_assert(LZ == LM - 2 && (NL / 2) * half == kBlock, "one node pair of one mirror pair per thread");
+  static_assert(LZ == LM - 2 && NL >= 2 && (NL / 2) * half == NT, "one node pair of one mirror pair per thread");
   static_assert(PM::rad(0) == 8 && PM::nst >= 2, "pipelined first stage");
   constexpr int PADL = 4;
   constexpr int LS = m + (m >> PADL);  // line stride in LDS
   auto pad = [](int i) { return i + (i >> PADL); };
   constexpr int sub = m >> 3, lsub = LM - 3;
-  constexpr int LPP = kBlock / sub;  // lines of one pass of first-stage butterflies (NL / 2)
+  constexpr int LPP = NT / sub;  // lines of one pass of first-stage butterflies (NL / 2)
   const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
-  const cx<T>* twm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
-  const cx<T>* twz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+  using ML = MirrorLds<LM, NT>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
-  const T* sn = static_cast<const T*>(I.sn);
+  // the item-invariant tables, copied once into LDS after the points (read
+  // at every item, they would otherwise wait on the L2 there)
+  cx<T>* twm = buf + ML::kPts;
+  cx<T>* twz = twm + ML::TWM;
+  T* snl = reinterpret_cast<T*>(twz + ML::TWZ);
+  {
+    const cx<T>* gm = static_cast<const cx<T>*>(I.tw) + I.fm.tw;
+    const cx<T>* gz = static_cast<const cx<T>*>(I.tw) + I.fz.tw;
+    for (int i = threadIdx.x; i < ML::TWM; i += NT) twm[i] = gm[i];
+    for (int i = threadIdx.x; i < ML::TWZ; i += NT) twz[i] = gz[i];
+    if constexpr (ML::SN) {
+      const T* gs = static_cast<const T*>(I.sn);
+      for (int i = threadIdx.x; i < nt; i += NT) snl[i] = gs[i];
+    }
+    __syncthreads();
+  }
+  auto sn_at = [&](int n) {
+    if constexpr (ML::SN) return snl[n];
+    return static_cast<const T*>(I.sn)[n];
+  };
   const int q = nt >> 2;
   // inputs r = 0, 1, 6, 7 of a butterfly: samples j + nt/2, j + 3nt/4, j, j + nt/4
   // (formed where used: nothing per thread is held across the item loop that
@@ -3043,7 +3090,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
     // held across it: the registers go to the later phases)
     T snr[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) snr[i] = sn[ns(i)];
+    for (int i = 0; i < 4; ++i) snr[i] = sn_at(ns(i));
     const cx<T> w1 = twm[j];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -3060,7 +3107,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
       for (int r = 0; r < 8; ++r) buf[pad(b * m + j + r * sub)] = v[r];
     }
     __syncthreads();
-    p2_stages<T, LM, 1, p2_l16_m(LM), PADL>(buf, twm, NL);
+    p2_stages<T, LM, 1, p2_l16_m(LM), PADL, NT>(buf, twm, NL);
     if (item + (int)gridDim.x < a.total) fetch(item + gridDim.x);
     {
       // last grid stage, in place: read, barrier, write in natural order
@@ -3068,7 +3115,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
       cx<T> lv[NB][RL];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        const int id = (int)threadIdx.x + u * kBlock;
+        const int id = (int)threadIdx.x + u * NT;
         const int b = id >> (LM - LRL), blk = id & ((m >> LRL) - 1);
         const cx<T>* p = buf + pad(b * m + blk * RL);
 #pragma unroll
@@ -3078,7 +3125,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
-        const int id = (int)threadIdx.x + u * kBlock;
+        const int id = (int)threadIdx.x + u * NT;
         const int b = id >> (LM - LRL), blk = id & ((m >> LRL) - 1);
         cx<T>* g = buf + b * LS;
         const int k0 = PM::natural(blk * RL);
@@ -3099,28 +3146,30 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
         const int L1 = mirror_line<true>(I, line0 + 2 * h + 1, &sh1);
         const double bl = I.b * (double)la * (double)la;
         double nup = sqrt_nt(line_ak<true>(I, L0) + bl);
+        // (the weight, halved on the Nyquist lane, rides on the node phase)
+        const double wla = wsc * (double)la * (la < half ? 1.0 : 0.5);
         PairWin<T, TAPS> pw;
         pair_window<T, TAPS, true>(nup, I, a, m, 0.0, pw);
-        double wl = wsc * (double)la * rcp_nt(nup);
+        pw.ph = cscl(pw.ph, T(wla * rcp_nt(nup)));
         cx<T> vp, vn;
         pair_values<T, TAPS, false>(buf + 2 * h * LS, m, pw, &vp, &vn);
         if (la < half) {
-          o[0] = cscl(vp, T(wl));
-          o[1] = cscl(vn, T(wl));
+          o[0] = vp;
+          o[1] = vn;
         } else {
-          o[0] = cscl(cadd(vp, vn), T(0.5 * wl));
+          o[0] = cadd(vp, vn);
         }
         if (!sh) {
           nup = sqrt_nt(line_ak<true>(I, L1) + bl);
           pair_window<T, TAPS, true>(nup, I, a, m, 0.0, pw);
-          wl = wsc * (double)la * rcp_nt(nup);
+          pw.ph = cscl(pw.ph, T(wla * rcp_nt(nup)));
         }
         pair_values<T, TAPS, false>(buf + (2 * h + 1) * LS, m, pw, &vp, &vn);
         if (la < half) {
-          o[2] = cscl(vp, T(wl));
-          o[3] = cscl(vn, T(wl));
+          o[2] = vp;
+          o[3] = vn;
         } else {
-          o[2] = cscl(cadd(vp, vn), T(0.5 * wl));
+          o[2] = cadd(vp, vn);
         }
       }
       __syncthreads();
@@ -3134,8 +3183,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft2_mirror(StageArgs a) {
       buf[pad(e1 + ln)] = cconj(o[3]);
     }
     __syncthreads();
-    p2_stages<T, LZ, 0, p2_l16_z(LZ), PADL>(buf, twz, NL);
-    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true, PADL>(buf, nz, NL, nz, 1, [&](int b, int blk, const auto& v) {
+    p2_stages<T, LZ, 0, p2_l16_z(LZ), PADL, NT>(buf, twz, NL);
+    fft_last_stage_p2<T, PZ::rad(PZ::nst - 1), true, PADL, NT>(buf, nz, NL, nz, 1, [&](int b, int blk, const auto& v) {
       constexpr int R = sizeof(v) / sizeof(v[0]);
       if (b >= nl) return;
       bool sh;
@@ -3393,14 +3442,14 @@ int num_cu() {
 
 // Workgroups of kBlock threads that one CU holds at once for this kernel and
 // LDS size (cached: the query is not free and the answer never changes).
-int resident_blocks(const void* kernel, size_t shmem) {
+int resident_blocks(const void* kernel, size_t shmem, int block = kBlock) {
   static std::mutex mu;
   static std::map<std::pair<const void*, size_t>, int> cache;
   std::lock_guard<std::mutex> lock(mu);
   auto it = cache.find({kernel, shmem});
   if (it != cache.end()) return it->second;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, shmem) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, shmem) != hipSuccess || per_cu < 1)
     per_cu = 1;
   cache[{kernel, shmem}] = per_cu;
   return per_cu;
@@ -3440,7 +3489,7 @@ hipError_t launch(K kernel, const char* name, StageArgs& a, size_t shmem, hipStr
 // for kernels that stride over their items themselves.
 template <typename K>
 hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t shmem, hipStream_t st,
-                             StageTimer* tm) {
+                             StageTimer* tm, int block = kBlock) {
   if (a.total <= 0) return hipSuccess;
   if (launch_faulted()) return hipErrorLaunchFailure;
   if (shmem > 65536) {
@@ -3448,10 +3497,10 @@ hipError_t launch_persistent(K kernel, const char* name, StageArgs& a, size_t sh
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
   }
-  const int cap = resident_blocks(reinterpret_cast<const void*>(kernel), shmem) * num_cu();
+  const int cap = resident_blocks(reinterpret_cast<const void*>(kernel), shmem, block) * num_cu();
   const int grid = a.total < cap ? a.total : cap;
   if (tm) tm->begin(name, st);
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), shmem, st, a);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, st, a);
   hipError_t e = hipGetLastError();
   if (tm) tm->end(st);
   return e;
@@ -3687,14 +3736,16 @@ struct Runner {
         // R on 3D plans with nz = m/4: line groups in mirror pairs, m = 2^8 .. 2^11
         const int lm = __builtin_ctz((unsigned)I.m);
         if (lm >= 8 && lm <= 11) {
-          a.total = cdiv(I.lines, 4096 / I.m);
+          // two waves per workgroup up to m = 1024 (one mirror pair there),
+          // four at m = 2048
+          const int nt_ = lm <= 10 ? 128 : 256;
+          a.total = cdiv(I.lines, 16 * nt_ / I.m);
           a.off[1] = a.total;
-          const size_t shm = (size_t)4096 * 17 / 16 * cs;
-          auto go = [&](auto kern) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm); };
-          if (lm == 8) return go(k_line_nufft2_mirror<TAPS, 8, 6>);
-          if (lm == 9) return go(k_line_nufft2_mirror<TAPS, 9, 7>);
-          if (lm == 10) return go(k_line_nufft2_mirror<TAPS, 10, 8>);
-          return go(k_line_nufft2_mirror<TAPS, 11, 9>);
+          auto go = [&](auto kern, int shm) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm, nt_); };
+          if (lm == 8) return go(k_line_nufft2_mirror<TAPS, 8, 6, 128>, MirrorLds<8, 128>::bytes);
+          if (lm == 9) return go(k_line_nufft2_mirror<TAPS, 9, 7, 128>, MirrorLds<9, 128>::bytes);
+          if (lm == 10) return go(k_line_nufft2_mirror<TAPS, 10, 8, 128>, MirrorLds<10, 128>::bytes);
+          return go(k_line_nufft2_mirror<TAPS, 11, 9, 256>, MirrorLds<11, 256>::bytes);
         }
       }
     }
