@@ -3065,13 +3065,18 @@ __global__ __launch_bounds__(NT, 4) void k_line_nufft2_mirror(StageArgs a) {
   cx<T>* outb = static_cast<cx<T>*>(a.out[0]);
   const int lines = I.lines;
   cx<T> pre[2][4];
+  // (where a wavefront's butterflies lie in one line, its line index is
+  // wave-uniform and taken into scalar registers, so that the line
+  // arithmetic and the row address run on the scalar unit)
+  constexpr bool WU = sub >= 64;
+  auto uni = [](int v) { return WU ? __builtin_amdgcn_readfirstlane(v) : v; };
   auto fetch = [&](int item) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int slot = item * NL + bb + u * LPP;
+      const int slot = uni(item * NL + bb + u * LPP);
       const bool ok = slot < lines;
       bool sh;
-      const cx<T>* gin = in + (size_t)(ok ? mirror_line<true>(I, slot, &sh) : 0) * nt;
+      const cx<T>* gin = in + (size_t)uni(ok ? mirror_line<true>(I, slot, &sh) : 0) * nt;
 #pragma unroll
       for (int i = 0; i < 4; ++i) pre[u][i] = ok ? gin[ns(i)] : mk(T(0), T(0));
     }
@@ -3137,13 +3142,16 @@ __global__ __launch_bounds__(NT, 4) void k_line_nufft2_mirror(StageArgs a) {
     {
       // interpolation (R: |l| = 1 .. nz/2, node pairs +-nu+): node pair p of
       // mirror pair h
-      const int h = (int)threadIdx.x >> (LZ - 1), la = ((int)threadIdx.x & (half - 1)) + 1;
+      // (h is wave-uniform from half = 64 on)
+      constexpr bool HU = half >= 64;
+      auto hu = [](int v) { return HU ? __builtin_amdgcn_readfirstlane(v) : v; };
+      const int h = hu((int)threadIdx.x >> (LZ - 1)), la = ((int)threadIdx.x & (half - 1)) + 1;
       const bool act = 2 * h < nl;
       cx<T> o[4] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
       if (act) {
         bool sh, sh1;
-        const int L0 = mirror_line<true>(I, line0 + 2 * h, &sh);
-        const int L1 = mirror_line<true>(I, line0 + 2 * h + 1, &sh1);
+        const int L0 = hu(mirror_line<true>(I, line0 + 2 * h, &sh));
+        const int L1 = hu(mirror_line<true>(I, line0 + 2 * h + 1, &sh1));
         const double bl = I.b * (double)la * (double)la;
         double nup = sqrt_nt(line_ak<true>(I, L0) + bl);
         // (the weight, halved on the Nyquist lane, rides on the node phase)
