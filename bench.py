@@ -23,6 +23,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -90,11 +91,20 @@ def roofline_of(name, nbytes, flops, ms):
     return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
 
 
+def code_of(text):
+    """C++ source text without its comments, whitespace runs collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and layout do not count, so
+    that recorded counters stay valid across edits that change no kernel."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "pat_internal.h"):
-        with open(os.path.join(ROOT, "paper_0808_3510_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0808_3510_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -552,7 +562,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="planar-256x256x512-to-256^3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16grid"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")

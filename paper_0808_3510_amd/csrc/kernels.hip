@@ -27,7 +27,7 @@
 //                 (k_line_nufft2_pipe: its software pipeline for c = 2;
 //                 k_line_nufft2_pipe_c: the same for sizes fixed at compile
 //                 time; k_line_nufft2_mirror: R on 3D plans with nz = m/4,
-//                 four lines per item in mirror pairs sharing node windows)
+//                 the lines of an item in mirror pairs sharing node windows)
 //   k_line_nufft1 depth DFT + spreading + transposed a2 fused per line in LDS
 //                 (k_line_nufft1_c: sizes fixed at compile time;
 //                 k_line_nufft1_w: one line per wavefront, FP32)
@@ -2982,9 +2982,9 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft2_
 }
 
 // k_line_nufft2_pipe_c for R on 3D plans whose depth lines are a quarter of
-// the grid lines (nz = m/4, m = 2^LM): a work item holds NL = 4096/m lines,
-// taken in mirror pairs (mirror_line), in 4096 padded points of LDS (34 KB,
-// four workgroups per CU).  Each of the 256 threads runs two first-stage
+// the grid lines (nz = m/4, m = 2^LM), with NT threads: a work item holds
+// NL = 16 NT/m lines, taken in mirror pairs (mirror_line), in 16 NT padded
+// points of LDS (four waves per SIMD).  Each thread runs two first-stage
 // butterflies, and in the interpolation one node pair of one mirror pair:
 // its window, phase and weight serve both lines (the two lines of a pair
 // with r = 0 form their own).  The last grid-FFT stage works in place: every

@@ -100,3 +100,13 @@ def test_counter_table_per_wave_and_busy(tmp_path):
     busy = 4 * 4096 * 1000.0 / (1024 * 2.4e9 * 100e-6)
     assert cells[11] == f"{busy:.2f}"
     assert cells[12] == "1.50"
+
+
+def test_code_hash_ignores_comments_not_code():
+    """The traffic table stays valid across comment edits of the kernels and
+    is dropped by any change of their code."""
+    b = _bench()
+    base = "int f(int x) {  // twice\n  return 2 * x; /* doubled */\n}\n"
+    assert b.code_of(base) == b.code_of("int f(int x) {\n  // other words\n  return 2 * x;\n}")
+    assert b.code_of(base) != b.code_of("int f(int x) {\n  return 3 * x;\n}")
+
