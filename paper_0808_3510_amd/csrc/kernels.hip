@@ -2999,29 +2999,33 @@ constexpr int twiddle_extent() {
   for (int s = 0; s + 1 < Pl::nst; ++s) r = Pl::rad(s) < r ? Pl::rad(s) : r;
   return L / r;
 }
-// LDS of k_line_nufft2_mirror (FP32) with NT threads: its 16 NT padded
-// points, the twiddles of both FFTs' twiddled stages and, where the
-// workgroups of four waves per SIMD still fit in 160 KB, the deconvolution
-// factors s_n.
-template <int LM, int NT>
+// Waves per SIMD of k_line_nufft2_mirror: four in FP32, two in FP64 (its
+// registers).
+template <typename T>
+constexpr int mirror_waves() { return sizeof(T) == 4 ? 4 : 2; }
+// LDS of k_line_nufft2_mirror with NT threads: its 16 NT padded points, the
+// twiddles of both FFTs' twiddled stages and, where the workgroups of
+// mirror_waves per SIMD still fit in 160 KB, the deconvolution factors s_n.
+template <typename T, int LM, int NT>
 struct MirrorLds {
-  static constexpr int m = 1 << LM, nt = m / 2, nz = m / 4, P = 16 * NT;
+  static constexpr int m = 1 << LM, nt = m / 2, nz = m / 4, P = 16 * NT, cs = 2 * (int)sizeof(T);
   static constexpr int TWM = twiddle_extent<P2Plan<LM, p2_l16_m(LM)>, m>();
   static constexpr int TWZ = twiddle_extent<P2Plan<LM - 2, p2_l16_z(LM - 2)>, nz>();
   static constexpr int kPts = P + (P >> 4);
-  static constexpr int kTw = (TWM + TWZ) * 8, kSn = nt * 4;
-  static constexpr int kGroups = 16 * 64 / NT;  // workgroups per CU at four waves per SIMD
-  static constexpr bool SN = (kPts * 8 + kTw + kSn) * kGroups <= 160 * 1024;
-  static constexpr int bytes = kPts * 8 + kTw + (SN ? kSn : 0);
+  static constexpr int kTw = (TWM + TWZ) * cs, kSn = nt * (int)sizeof(T);
+  static constexpr int kGroups = 4 * mirror_waves<T>() * 64 / NT;  // workgroups per CU
+  static constexpr bool SN = (kPts * cs + kTw + kSn) * kGroups <= 160 * 1024;
+  static constexpr int bytes = kPts * cs + kTw + (SN ? kSn : 0);
+  static constexpr bool fits = bytes * kGroups <= 160 * 1024;
 };
-static_assert(MirrorLds<10, 256>::TWM == 128 && MirrorLds<10, 256>::TWZ == 64 && MirrorLds<10, 256>::SN &&
-                  !MirrorLds<11, 256>::SN && MirrorLds<11, 256>::bytes * 4 <= 160 * 1024 &&
-                  MirrorLds<10, 128>::bytes * 8 <= 160 * 1024,
-              "four waves per SIMD");
+static_assert(MirrorLds<float, 10, 256>::TWM == 128 && MirrorLds<float, 10, 256>::TWZ == 64 &&
+                  MirrorLds<float, 10, 256>::SN && !MirrorLds<float, 11, 256>::SN &&
+                  MirrorLds<float, 11, 256>::fits && MirrorLds<float, 10, 128>::fits &&
+                  MirrorLds<double, 10, 128>::fits && MirrorLds<double, 11, 256>::fits,
+              "the resident waves per SIMD fit in LDS");
 
-template <int TAPS, int LM, int LZ, int NT>
-__global__ __launch_bounds__(NT, 4) void k_line_nufft2_mirror(StageArgs a) {
-  using T = float;
+template <typename T, int TAPS, int LM, int LZ, int NT>
+__global__ __launch_bounds__(NT, mirror_waves<T>()) void k_line_nufft2_mirror(StageArgs a) {
   const Inst& I = *a.inst[0];
   constexpr int m = 1 << LM, nt = m / 2, nz = 1 << LZ, NL = 16 * NT / m, half = nz / 2;
   using PM = P2Plan<LM, p2_l16_m(LM)>;
@@ -3034,7 +3038,7 @@ __global__ __launch_bounds__(NT, 4) void k_line_nufft2_mirror(StageArgs a) {
   constexpr int sub = m >> 3, lsub = LM - 3;
   constexpr int LPP = NT / sub;  // lines of one pass of first-stage butterflies (NL / 2)
   const int j = (int)threadIdx.x & (sub - 1), bb = (int)threadIdx.x >> lsub;
-  using ML = MirrorLds<LM, NT>;
+  using ML = MirrorLds<T, LM, NT>;
   cx<T>* buf = reinterpret_cast<cx<T>*>(pat_smem);
   // the item-invariant tables, copied once into LDS after the points (read
   // at every item, they would otherwise wait on the L2 there)
@@ -3737,7 +3741,7 @@ struct Runner {
   }
   hipError_t nufft2(const void* const* in, void* const* out, int mode) {
     StageArgs a = base(IT_LF, true, mode, in, out);
-    if constexpr (sizeof(T) == 4 && P2 && TAPS > 0) {
+    if constexpr (P2 && TAPS > 0) {
       const Inst& I = h[0];
       if (n == 1 && !a.counter && a.pair_ok && mode == 0 && I.m == 2 * I.nt && 4 * I.nz == I.m && I.n2 >= 4 &&
           I.fm.nst >= 2 && I.fm.rad[0] == 8) {
@@ -3750,10 +3754,10 @@ struct Runner {
           a.total = cdiv(I.lines, 16 * nt_ / I.m);
           a.off[1] = a.total;
           auto go = [&](auto kern, int shm) { return launch_persistent(kern, "nufft_fused", a, shm, st, tm, nt_); };
-          if (lm == 8) return go(k_line_nufft2_mirror<TAPS, 8, 6, 128>, MirrorLds<8, 128>::bytes);
-          if (lm == 9) return go(k_line_nufft2_mirror<TAPS, 9, 7, 128>, MirrorLds<9, 128>::bytes);
-          if (lm == 10) return go(k_line_nufft2_mirror<TAPS, 10, 8, 128>, MirrorLds<10, 128>::bytes);
-          return go(k_line_nufft2_mirror<TAPS, 11, 9, 256>, MirrorLds<11, 256>::bytes);
+          if (lm == 8) return go(k_line_nufft2_mirror<T, TAPS, 8, 6, 128>, MirrorLds<T, 8, 128>::bytes);
+          if (lm == 9) return go(k_line_nufft2_mirror<T, TAPS, 9, 7, 128>, MirrorLds<T, 9, 128>::bytes);
+          if (lm == 10) return go(k_line_nufft2_mirror<T, TAPS, 10, 8, 128>, MirrorLds<T, 10, 128>::bytes);
+          return go(k_line_nufft2_mirror<T, TAPS, 11, 9, 256>, MirrorLds<T, 11, 256>::bytes);
         }
       }
     }
