@@ -1418,6 +1418,31 @@ __device__ __forceinline__ void seg_step(const WaveSeg& s, float& x, float& y) {
   }
 }
 
+template <int BIT, int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ void seg_step2(const WaveSeg& s, float& x, float& y, float& u, float& v) {
+  if (s.use & BIT) {
+    const float tx = x + dpp_mov<CTRL, ROWS>(x);
+    const float ty = y + dpp_mov<CTRL, ROWS>(y);
+    const float tu = u + dpp_mov<CTRL, ROWS>(u);
+    const float tv = v + dpp_mov<CTRL, ROWS>(v);
+    const bool on = (s.on & BIT) != 0;
+    x = on ? tx : x;
+    y = on ? ty : y;
+    u = on ? tu : u;
+    v = on ? tv : v;
+  }
+}
+
+// The same sum over two pairs (x, y) and (u, v) with the same segments.
+__device__ __forceinline__ void seg_sum2(const WaveSeg& s, float& x, float& y, float& u, float& v) {
+  seg_step2<1, 0x111>(s, x, y, u, v);
+  seg_step2<2, 0x112>(s, x, y, u, v);
+  seg_step2<4, 0x114>(s, x, y, u, v);
+  seg_step2<8, 0x118>(s, x, y, u, v);
+  seg_step2<16, 0x142, 0xa>(s, x, y, u, v);
+  seg_step2<32, 0x143, 0xc>(s, x, y, u, v);
+}
+
 // Segmented inclusive sum of (x, y) over the lanes (see WaveSeg).
 __device__ __forceinline__ void seg_sum(const WaveSeg& s, float& x, float& y) {
   seg_step<1, 0x111>(s, x, y);         // row_shr:1
@@ -1499,6 +1524,45 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
+}
+
+// Both passes of a batch at once, for the common case that spread_line_wave
+// checks: no node on a grid point (so the passes share their segments),
+// neither pass's writers wrap past the end of the line, and the cells of the
+// two passes are disjoint.  Each cell then receives the same terms in the
+// same order as in two separate passes, and a round's two read-add-write
+// chains overlap.  rp, rm: first taps mod m.
+template <int TAPS>
+__device__ __forceinline__ void spread_pair_wave(cx<float>* G, int rp, int rm, bool wr, cx<float> vp, cx<float> vm,
+                                                 const float* w, const float* wm, const WaveSeg& sg) {
+  cx<float>* gp = G + rp;
+  cx<float>* gm = G + rm;
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t) {
+    float xp = w[t] * vp.x, yp = w[t] * vp.y, xm = wm[t] * vm.x, ym = wm[t] * vm.y;
+    seg_sum2(sg, xp, yp, xm, ym);
+    if (wr) {
+      const cx<float> a = gp[t], b = gm[t];
+      gp[t] = mk(a.x + xp, a.y + yp);
+      gm[t] = mk(b.x + xm, b.y + ym);
+    }
+    // the next round's reads come after this round's writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+}
+
+// Whether the cells of the two passes of a batch are disjoint modulo m:
+// + nodes cover [jf, jl + TAPS - 1] (first taps monotone over the active
+// lanes, jf at lane 0, jl at the last), their mirrors at most
+// [-(jl + TAPS - 1), -jf + 1]; both spans shorter than m.
+template <int TAPS>
+__device__ __forceinline__ bool passes_disjoint(int jf, int jl, int m) {
+  const int lo_p = jf, len_p = jl + TAPS - jf;
+  const int lo_m = -(jl + TAPS - 1), len_m = jl - jf + TAPS + 1;
+  if (len_p + len_m > m) return false;
+  int d = (lo_m - lo_p) % m;
+  d += d < 0 ? m : 0;
+  return d >= len_p && d + len_m <= m;
 }
 
 // A few nodes (n <= 64 / TAPS, in lanes 0 .. n-1: first tap j0, value v,
@@ -1619,11 +1683,30 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       // reverse), so the two passes share their segments unless a node sits
       // on a grid point
       const WaveSeg sg = pass_segments(j0, act);
-      spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
-      if (__any(act && ongrid)) {
-        spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
+      const bool anyon = __any(act && ongrid);
+      // (lanes 0 and nact - 1 hold the extreme first taps: read them on the
+      // scalar unit)
+      const int jf = __builtin_amdgcn_readlane(j0, 0), jl = __builtin_amdgcn_readlane(j0, nact - 1);
+      int rp, rm;
+      if constexpr (P2) {
+        rp = j0 & (m - 1);
+        rm = jm & (m - 1);
       } else {
-        spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, sg);
+        rp = j0 % m;
+        rp += rp < 0 ? m : 0;
+        rm = jm % m;
+        rm += rm < 0 ? m : 0;
+      }
+      const bool wr = act && sg.tail;
+      if (!anyon && passes_disjoint<TAPS>(jf, jl, m) && !__any(wr && (rp > m - TAPS || rm > m - TAPS))) {
+        spread_pair_wave<TAPS>(G, rp, rm, wr, vp, vm, w, wm, sg);
+      } else {
+        spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
+        if (anyon) {
+          spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
+        } else {
+          spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, sg);
+        }
       }
     }
   }
