@@ -1999,7 +1999,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2(StageArgs a) {
 // the next tile is stored into LDS.  LL > 0 fixes the transform length at
 // 2^LL (and its FFT stages) at compile time, in all three pipelines.
 template <typename T, int RS, int LL = 0>
-__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArgs a);
+__global__ __launch_bounds__(kBlock, RS == 0 ? (sizeof(T) == 4 ? 4 : 2) : 1) void k_tr_x1_pipe(StageArgs a);
 
 // k_tr_x2 as a software pipeline for one instance whose tile is at most
 // kPipeU column pairs per thread (n2 * tb / 2 <= kPipeU * kBlock, tb even): a
@@ -2009,10 +2009,17 @@ __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArg
 // written back.  The output positions sit in LDS beside the twiddles (a
 // table read from memory in the store loop would wait for those loads).
 constexpr int kPipeU = 8;
-// tile width of the FP32 plans (16 columns, 8 once a tile of 2^9-point
-// columns would pass 64 KB of LDS), fixed with the length in the instances
-// that take it at compile time
-constexpr int pipe_tb(int ll) { return ll >= 9 ? 8 : 16; }
+// tile width of the plans (FP32: 16 columns, 8 once a tile of 2^9-point
+// columns would pass 64 KB of LDS; FP64: 8, then 4), fixed with the length in
+// the instances that take it at compile time
+template <typename T>
+constexpr int pipe_tb(int ll) { return sizeof(T) == 4 ? (ll >= 9 ? 8 : 16) : (ll >= 9 ? 4 : 8); }
+// registers per thread for a prefetched tile of 2^LL points by tb columns
+// (LL > 0), or for the largest tile a run-time length may have
+template <int LL>
+constexpr int pipe_units(int per_col) {
+  return LL > 0 ? ((1 << LL) * per_col + kBlock - 1) / kBlock : 0;
+}
 template <typename T, int RS, int LL = 0>
 __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
@@ -2024,17 +2031,18 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   const int32_t* perm = I.perm + I.f2.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb<T>(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + tb - 1) / tb;
   const bool inv = a.mode != 0;
   cx<T>* base = static_cast<cx<T>*>(a.out[0]);
-  cx<T> pre[2 * kPipeU];
+  constexpr int PU = LL > 0 ? pipe_units<LL>(pipe_tb<T>(LL) / 2) : kPipeU;  // column pairs per thread
+  cx<T> pre[2 * PU];
   auto fetch = [&](int item) {
     const int k1 = item / ntile;
     const int t0 = (item - k1 * ntile) * tb;
     const cx<T>* io = base + (size_t)k1 * L * len + t0;
 #pragma unroll
-    for (int u = 0; u < kPipeU; ++u) {
+    for (int u = 0; u < PU; ++u) {
       const int e = (int)threadIdx.x + u * kBlock;
       pre[2 * u] = pre[2 * u + 1] = mk(T(0), T(0));
       if (e < L * hb) {
@@ -2048,7 +2056,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
   if (item < a.total) fetch(item);
   for (; item < a.total; item += gridDim.x) {
 #pragma unroll
-    for (int u = 0; u < kPipeU; ++u) {
+    for (int u = 0; u < PU; ++u) {
       const int e = (int)threadIdx.x + u * kBlock;
       if (e < L * hb) {
         buf[2 * e] = inv ? cconj(pre[2 * u]) : pre[2 * u];
@@ -2075,7 +2083,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_x2_pipe(StageArgs a) {
 }
 
 template <typename T, int RS, int LL>
-__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArgs a) {
+__global__ __launch_bounds__(kBlock, RS == 0 ? (sizeof(T) == 4 ? 4 : 2) : 1) void k_tr_x1_pipe(StageArgs a) {
   [[maybe_unused]] constexpr bool P2 = RS == 0;
   const Inst& I = *a.inst[0];
   const int L = LL > 0 ? 1 << LL : I.n1;
@@ -2089,18 +2097,19 @@ __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArg
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb<T>(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const size_t rstride = (size_t)I.n2 * len;
   const T* in = static_cast<const T*>(a.in[0]);
   cx<T>* out = static_cast<cx<T>*>(a.out[0]);
-  cx<T> pre[2 * kPipeU];
+  constexpr int PU = LL > 0 ? pipe_units<LL>(pipe_tb<T>(LL) / 2) : kPipeU;  // column pairs per thread
+  cx<T> pre[2 * PU];
   auto fetch = [&](int item) {
     const int x2 = item / ntile;
     const int t0 = (item - x2 * ntile) * 2 * tb;
     const T* in0 = in + (size_t)x2 * len + t0;
 #pragma unroll
-    for (int u = 0; u < kPipeU; ++u) {
+    for (int u = 0; u < PU; ++u) {
       const int e = (int)threadIdx.x + u * kBlock;
       pre[2 * u] = pre[2 * u + 1] = mk(T(0), T(0));
       if (e < L * hb) {
@@ -2125,7 +2134,7 @@ __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_x1_pipe(StageArg
     const T* cws = cws0 + (it & 1) * ew;
     const int cb2 = cut && I.n2 > 1 ? cut_band(x2, I.n2, I.cut_e) : I.cut_e;
 #pragma unroll
-    for (int u = 0; u < kPipeU; ++u) {
+    for (int u = 0; u < PU; ++u) {
       const int e = (int)threadIdx.x + u * kBlock;
       if (e < L * hb) {
         cx<T> v0 = pre[2 * u], v1 = pre[2 * u + 1];
@@ -2277,7 +2286,7 @@ __global__ __launch_bounds__(kBlock) void k_tr_c2r_k1(StageArgs a) {
 // without a cut-off on this pass, len a multiple of 4, tb even and
 // n1 * tb <= 2 kPipeU * kBlock bins per tile.
 template <typename T, int RS, int LL = 0>
-__global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_c2r_pipe(StageArgs a) {
+__global__ __launch_bounds__(kBlock, RS == 0 ? (sizeof(T) == 4 ? 4 : 2) : 1) void k_tr_c2r_pipe(StageArgs a) {
   const Inst& I = *a.inst[0];
   const int L = LL > 0 ? 1 << LL : I.n1, half = L / 2;
   cx<T>* tw = reinterpret_cast<cx<T>*>(pat_smem);
@@ -2287,12 +2296,12 @@ __global__ __launch_bounds__(kBlock, RS == 0 ? 4 : 1) void k_tr_c2r_pipe(StageAr
   const int32_t* perm = I.perm + I.f1.perm;
   for (int e = threadIdx.x; e < L; e += kBlock) pos[e] = perm[e];
   const int len = a.len_nz ? I.nz : I.nt;
-  const int tb = LL > 0 ? pipe_tb(LL) : I.tb, hb = tb / 2;
+  const int tb = LL > 0 ? pipe_tb<T>(LL) : I.tb, hb = tb / 2;
   const int ntile = (len + 2 * tb - 1) / (2 * tb);
   const size_t rstride = (size_t)I.n2 * len;
   const cx<T>* in = static_cast<const cx<T>*>(a.in[0]);
   T* out = static_cast<T*>(a.out[0]);
-  constexpr int U = 2 * kPipeU;
+  constexpr int U = LL > 0 ? pipe_units<LL>(pipe_tb<T>(LL)) : 2 * kPipeU;  // bins per thread
   cx<T> pre[U];
   auto fetch = [&](int item) {
     const int x2 = item / ntile;
@@ -3684,13 +3693,14 @@ struct Runner {
     return mx;
   }
 
-  // The pipelined transverse kernels run for one FP32 instance (double
-  // registers of a prefetched tile would halve occupancy); lengths of 128, 256
-  // and 512 points with the plan's tile width take the compile-time instances.
+  // The pipelined transverse kernels run for one instance; lengths of 128,
+  // 256 and 512 points with the plan's tile width take the compile-time
+  // instances (FP64 only these: its run-time-size pipelines, sized for the
+  // largest tile, would spill), other FP32 lengths the run-time-size ones.
   hipError_t x1(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_X1, nz, 0, in, out);
     const int len = nz ? h[0].nz : h[0].nt;
-    if constexpr (sizeof(T) == 4) {
+    {
       if (n == 1 && !a.counter && len % 4 == 0 && h[0].tb % 2 == 0 && h[0].n1 * (h[0].tb / 2) <= kPipeU * kBlock) {
         const size_t ew = (size_t)(h[0].cut_e + 1) * (h[0].cut_e + 1);
         const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t) +
@@ -3698,11 +3708,11 @@ struct Runner {
         auto go = [&](auto kern) { return launch_persistent(kern, "dft_x1", a, shm, st, tm); };
         if constexpr (RS == 0) {
           const int L = h[0].n1, tb = h[0].tb;
-          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_x1_pipe<T, RS, 7>);
-          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_x1_pipe<T, RS, 8>);
-          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_x1_pipe<T, RS, 9>);
+          if (L == 128 && tb == pipe_tb<T>(7)) return go(k_tr_x1_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb<T>(8)) return go(k_tr_x1_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb<T>(9)) return go(k_tr_x1_pipe<T, RS, 9>);
         }
-        return go(k_tr_x1_pipe<T, RS>);
+        if constexpr (sizeof(T) == 4) return go(k_tr_x1_pipe<T, RS>);
       }
     }
     return launch(k_tr_x1_r2c<T, RS>, "dft_x1", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }), st,
@@ -3711,17 +3721,17 @@ struct Runner {
   hipError_t x2(void* const* io, bool nz, int inv) {
     StageArgs a = base(IT_X2, nz, inv, io, io);
     const char* name = inv ? "idft_x2" : "dft_x2";
-    if constexpr (sizeof(T) == 4) {
+    {
       if (n == 1 && !a.counter && h[0].tb % 2 == 0 && h[0].n2 * (h[0].tb / 2) <= kPipeU * kBlock) {
         const size_t shm = lds_tile_x2(h[0], cs) + (size_t)((h[0].n2 + 3) & ~3) * sizeof(int32_t);
         auto go = [&](auto kern) { return launch_persistent(kern, name, a, shm, st, tm); };
         if constexpr (RS == 0) {
           const int L = h[0].n2, tb = h[0].tb;
-          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_x2_pipe<T, RS, 7>);
-          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_x2_pipe<T, RS, 8>);
-          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_x2_pipe<T, RS, 9>);
+          if (L == 128 && tb == pipe_tb<T>(7)) return go(k_tr_x2_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb<T>(8)) return go(k_tr_x2_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb<T>(9)) return go(k_tr_x2_pipe<T, RS, 9>);
         }
-        return go(k_tr_x2_pipe<T, RS>);
+        if constexpr (sizeof(T) == 4) return go(k_tr_x2_pipe<T, RS>);
       }
     }
     return launch(k_tr_x2<T, RS>, name, a, max_over([](const Inst& I) { return lds_tile_x2(I, cs); }), st, tm);
@@ -3729,18 +3739,18 @@ struct Runner {
   hipError_t c2r(const void* const* in, void* const* out, bool nz) {
     StageArgs a = base(IT_C2R, nz, 0, in, out);
     const int len = nz ? h[0].nz : h[0].nt;
-    if constexpr (sizeof(T) == 4) {
+    {
       if (n == 1 && !a.counter && !(!nz && h[0].cut_e) && len % 4 == 0 && h[0].tb % 2 == 0 &&
           h[0].n1 * h[0].tb <= 2 * kPipeU * kBlock) {
         const size_t shm = (size_t)h[0].n1 * (h[0].tb + 1) * cs + (size_t)((h[0].n1 + 3) & ~3) * sizeof(int32_t);
         auto go = [&](auto kern) { return launch_persistent(kern, "idft_x1_c2r", a, shm, st, tm); };
         if constexpr (RS == 0) {
           const int L = h[0].n1, tb = h[0].tb;
-          if (L == 128 && tb == pipe_tb(7)) return go(k_tr_c2r_pipe<T, RS, 7>);
-          if (L == 256 && tb == pipe_tb(8)) return go(k_tr_c2r_pipe<T, RS, 8>);
-          if (L == 512 && tb == pipe_tb(9)) return go(k_tr_c2r_pipe<T, RS, 9>);
+          if (L == 128 && tb == pipe_tb<T>(7)) return go(k_tr_c2r_pipe<T, RS, 7>);
+          if (L == 256 && tb == pipe_tb<T>(8)) return go(k_tr_c2r_pipe<T, RS, 8>);
+          if (L == 512 && tb == pipe_tb<T>(9)) return go(k_tr_c2r_pipe<T, RS, 9>);
         }
-        return go(k_tr_c2r_pipe<T, RS>);
+        if constexpr (sizeof(T) == 4) return go(k_tr_c2r_pipe<T, RS>);
       }
     }
     return launch(k_tr_c2r_k1<T, RS>, "idft_x1_c2r", a, max_over([](const Inst& I) { return lds_tile_x1(I, cs); }),
