@@ -1368,6 +1368,14 @@ template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ float dpp_mov(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, ROWS, 0xf, true));
 }
+// (a double as its two halves)
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, ROWS, 0xf, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Segments of a key that is monotone over the 64 lanes (equal keys are
 // contiguous).  Bit k of `on` is set when the lane adds in step k of the
@@ -1407,24 +1415,24 @@ __device__ __forceinline__ WaveSeg wave_segments(int key) {
   return s;
 }
 
-template <int BIT, int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ void seg_step(const WaveSeg& s, float& x, float& y) {
+template <int BIT, int CTRL, int ROWS = 0xf, typename F>
+__device__ __forceinline__ void seg_step(const WaveSeg& s, F& x, F& y) {
   if (s.use & BIT) {
-    const float tx = x + dpp_mov<CTRL, ROWS>(x);
-    const float ty = y + dpp_mov<CTRL, ROWS>(y);
+    const F tx = x + dpp_mov<CTRL, ROWS>(x);
+    const F ty = y + dpp_mov<CTRL, ROWS>(y);
     const bool on = (s.on & BIT) != 0;
     x = on ? tx : x;
     y = on ? ty : y;
   }
 }
 
-template <int BIT, int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ void seg_step2(const WaveSeg& s, float& x, float& y, float& u, float& v) {
+template <int BIT, int CTRL, int ROWS = 0xf, typename F>
+__device__ __forceinline__ void seg_step2(const WaveSeg& s, F& x, F& y, F& u, F& v) {
   if (s.use & BIT) {
-    const float tx = x + dpp_mov<CTRL, ROWS>(x);
-    const float ty = y + dpp_mov<CTRL, ROWS>(y);
-    const float tu = u + dpp_mov<CTRL, ROWS>(u);
-    const float tv = v + dpp_mov<CTRL, ROWS>(v);
+    const F tx = x + dpp_mov<CTRL, ROWS>(x);
+    const F ty = y + dpp_mov<CTRL, ROWS>(y);
+    const F tu = u + dpp_mov<CTRL, ROWS>(u);
+    const F tv = v + dpp_mov<CTRL, ROWS>(v);
     const bool on = (s.on & BIT) != 0;
     x = on ? tx : x;
     y = on ? ty : y;
@@ -1434,7 +1442,8 @@ __device__ __forceinline__ void seg_step2(const WaveSeg& s, float& x, float& y, 
 }
 
 // The same sum over two pairs (x, y) and (u, v) with the same segments.
-__device__ __forceinline__ void seg_sum2(const WaveSeg& s, float& x, float& y, float& u, float& v) {
+template <typename F>
+__device__ __forceinline__ void seg_sum2(const WaveSeg& s, F& x, F& y, F& u, F& v) {
   seg_step2<1, 0x111>(s, x, y, u, v);
   seg_step2<2, 0x112>(s, x, y, u, v);
   seg_step2<4, 0x114>(s, x, y, u, v);
@@ -1444,7 +1453,8 @@ __device__ __forceinline__ void seg_sum2(const WaveSeg& s, float& x, float& y, f
 }
 
 // Segmented inclusive sum of (x, y) over the lanes (see WaveSeg).
-__device__ __forceinline__ void seg_sum(const WaveSeg& s, float& x, float& y) {
+template <typename F>
+__device__ __forceinline__ void seg_sum(const WaveSeg& s, F& x, F& y) {
   seg_step<1, 0x111>(s, x, y);         // row_shr:1
   seg_step<2, 0x112>(s, x, y);         // row_shr:2
   seg_step<4, 0x114>(s, x, y);         // row_shr:4
@@ -1467,9 +1477,9 @@ __device__ __forceinline__ WaveSeg pass_segments(int j0, bool act) {
   return wave_segments(act ? j0 : (0x40000000 + (int)(threadIdx.x & 63)));
 }
 
-template <int TAPS, bool P2>
-__device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bool act, int nact, cx<float> v,
-                                                 const float* w, const WaveSeg& sg) {
+template <typename T, int TAPS, bool P2>
+__device__ __forceinline__ void spread_pass_wave(cx<T>* G, int m, int j0, bool act, int nact, cx<T> v, const T* w,
+                                                 const WaveSeg& sg) {
   const int L = (int)(threadIdx.x & 63);
   const int jf = __shfl(j0, 0, 64), jl = __shfl(j0, nact - 1, 64);
   const bool distinct = (jf > jl ? jf - jl : jl - jf) < m;
@@ -1482,8 +1492,8 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
   }
   const bool wr = act && sg.tail;
   const bool flat = distinct && !__any(wr && r > m - TAPS);
-  cx<float>* g = G + r;
-  auto sum = [&](int t, float& x, float& y) {
+  cx<T>* g = G + r;
+  auto sum = [&](int t, T& x, T& y) {
     x = w[t] * v.x;
     y = w[t] * v.y;
     seg_sum(sg, x, y);
@@ -1491,7 +1501,7 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
   if (flat) {
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) {
-      float x, y;
+      T x, y;
       sum(t, x, y);
       if (wr) {
         g[t].x += x;
@@ -1503,7 +1513,7 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
   } else {
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) {
-      float x, y;
+      T x, y;
       sum(t, x, y);
       int c = r + t;
       c -= c >= m ? m : 0;
@@ -1532,17 +1542,17 @@ __device__ __forceinline__ void spread_pass_wave(cx<float>* G, int m, int j0, bo
 // two passes are disjoint.  Each cell then receives the same terms in the
 // same order as in two separate passes, and a round's two read-add-write
 // chains overlap.  rp, rm: first taps mod m.
-template <int TAPS>
-__device__ __forceinline__ void spread_pair_wave(cx<float>* G, int rp, int rm, bool wr, cx<float> vp, cx<float> vm,
-                                                 const float* w, const float* wm, const WaveSeg& sg) {
-  cx<float>* gp = G + rp;
-  cx<float>* gm = G + rm;
+template <typename T, int TAPS>
+__device__ __forceinline__ void spread_pair_wave(cx<T>* G, int rp, int rm, bool wr, cx<T> vp, cx<T> vm, const T* w,
+                                                 const T* wm, const WaveSeg& sg) {
+  cx<T>* gp = G + rp;
+  cx<T>* gm = G + rm;
 #pragma unroll
   for (int t = 0; t < TAPS; ++t) {
-    float xp = w[t] * vp.x, yp = w[t] * vp.y, xm = wm[t] * vm.x, ym = wm[t] * vm.y;
+    T xp = w[t] * vp.x, yp = w[t] * vp.y, xm = wm[t] * vm.x, ym = wm[t] * vm.y;
     seg_sum2(sg, xp, yp, xm, ym);
     if (wr) {
-      const cx<float> a = gp[t], b = gm[t];
+      const cx<T> a = gp[t], b = gm[t];
       gp[t] = mk(a.x + xp, a.y + yp);
       gm[t] = mk(b.x + xm, b.y + ym);
     }
@@ -1568,17 +1578,17 @@ __device__ __forceinline__ bool passes_disjoint(int jf, int jl, int m) {
 // A few nodes (n <= 64 / TAPS, in lanes 0 .. n-1: first tap j0, value v,
 // weights w) spread tap-parallel: lane k TAPS + t adds tap t of node k, one
 // node per round.
-template <int TAPS, bool P2>
-__device__ __forceinline__ void spread_few_wave(cx<float>* G, int m, int n, int j0, cx<float> v, const float* w) {
+template <typename T, int TAPS, bool P2>
+__device__ __forceinline__ void spread_few_wave(cx<T>* G, int m, int n, int j0, cx<T> v, const T* w) {
   const int L = (int)(threadIdx.x & 63);
   const int k = L / TAPS, t = L - k * TAPS;
   const int kk = k < n ? k : 0;
   const int jk = __shfl(j0, kk, 64);
-  const float vx = __shfl(v.x, kk, 64), vy = __shfl(v.y, kk, 64);
-  float wt = 0.f;
+  const T vx = __shfl(v.x, kk, 64), vy = __shfl(v.y, kk, 64);
+  T wt = T(0);
 #pragma unroll
   for (int i = 0; i < TAPS; ++i) {
-    const float wi = __shfl(w[i], kk, 64);
+    const T wi = __shfl(w[i], kk, 64);
     wt = t == i ? wi : wt;
   }
   int c;
@@ -1612,13 +1622,17 @@ __device__ __forceinline__ void spread_few_wave(cx<float>* G, int m, int n, int 
 // fget(l_index) reads the line's depth spectrum (DFT order).  A batch of at
 // most 64 / (2 TAPS) values of |l| (the last one of mode 1) spreads
 // tap-parallel.
-template <int TAPS, bool P2, typename Fget>
+template <typename T, int TAPS, bool P2, typename Fget>
 __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs& a, int line, int mode, int m, int nz,
-                                                 cx<float>* G, Fget fget) {
+                                                 cx<T>* G, Fget fget) {
   static_assert(TAPS % 2 == 0, "mirrored windows need an even tap count");
   const int L = (int)(threadIdx.x & 63);
-  float4* G4 = reinterpret_cast<float4*>(G);
-  for (int e = L; e < m / 2; e += 64) G4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (sizeof(T) == 4) {
+    float4* G4 = reinterpret_cast<float4*>(G);
+    for (int e = L; e < m / 2; e += 64) G4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    for (int e = L; e < m; e += 64) G[e] = mk(T(0), T(0));
+  }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int half = nz / 2;
   const int q0 = mode == 0 ? 1 : 0;
@@ -1630,8 +1644,8 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
     const bool act = L < nact;
     const int la = act ? q0 + base + L : q0;
     const double nup = sqrt_nt(Ak + I.b * (double)la * (double)la);
-    const cx<float> ph = phase_mpi<float>(nup);
-    cx<float> qp, qm;
+    const cx<T> ph = phase_mpi<T>(nup);
+    cx<T> qp, qm;
     double cf;
     if (mode == 0) {
       const bool nyq = la == half;
@@ -1639,21 +1653,21 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       qm = fget(nyq ? half : nz - la);
       cf = wsc * (double)la * rcp_nt(nup) * (nyq ? 0.5 : 1.0);
     } else {
-      cx<float> q = fget(la);
+      cx<T> q = fget(la);
       if (la != 0 && la != half) q = cadd(q, fget(nz - la));
       qp = qm = q;
       cf = 0.5 * I.scale;
     }
-    const float cff = act ? (float)cf : 0.f;
-    const cx<float> vp = cscl(cmul(cconj(qp), ph), cff);
-    const cx<float> vm = cscl(cmul(cconj(qm), cconj(ph)), cff);
+    const T cff = act ? (T)cf : T(0);
+    const cx<T> vp = cscl(cmul(cconj(qp), ph), cff);
+    const cx<T> vm = cscl(cmul(cconj(qm), cconj(ph)), cff);
     // +nu+: first tap j0, offset x, weights w; -nu+ mirrored (see above)
     int j0;
     const double d = tap_origin(I.c * nup, I.ck, &j0);
-    const float x = (float)(2.0 * d + 1.0);
+    const T x = (T)(2.0 * d + 1.0);
     const bool ongrid = d == -1.0;
-    float w[TAPS], wm[TAPS];
-    tap_weights_pairs<float, TAPS>(a, x, w);
+    T w[TAPS], wm[TAPS];
+    tap_weights_pairs<T, TAPS>(a, x, w);
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
     const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
@@ -1662,22 +1676,22 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       const int n2 = 2 * nact;
       const int src = L < nact ? L : L - nact;
       const bool neg = L >= nact;
-      float ws[TAPS];
+      T ws[TAPS];
 #pragma unroll
       for (int t = 0; t < TAPS; ++t) {
-        const float a0 = __shfl(w[t], src, 64), a1 = __shfl(wm[t], src, 64);
+        const T a0 = __shfl(w[t], src, 64), a1 = __shfl(wm[t], src, 64);
         ws[t] = neg ? a1 : a0;
       }
       // (every shuffle runs on all lanes, then each lane selects: a shuffle
       // inside one arm of a branch would read lanes the branch left inactive)
       const int jsp = __shfl(j0, src, 64), jsm = __shfl(jm, src, 64);
-      const float vpx = __shfl(vp.x, src, 64), vpy = __shfl(vp.y, src, 64);
-      const float vmx = __shfl(vm.x, src, 64), vmy = __shfl(vm.y, src, 64);
+      const T vpx = __shfl(vp.x, src, 64), vpy = __shfl(vp.y, src, 64);
+      const T vmx = __shfl(vm.x, src, 64), vmy = __shfl(vm.y, src, 64);
       const int js = neg ? jsm : jsp;
-      cx<float> vs;
+      cx<T> vs;
       vs.x = neg ? vmx : vpx;
       vs.y = neg ? vmy : vpy;
-      spread_few_wave<TAPS, P2>(G, m, n2, js, vs, ws);
+      spread_few_wave<T, TAPS, P2>(G, m, n2, js, vs, ws);
     } else {
       // equal first taps of +nu+ give equal first taps of -nu+ (and the
       // reverse), so the two passes share their segments unless a node sits
@@ -1699,13 +1713,13 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       }
       const bool wr = act && sg.tail;
       if (!anyon && passes_disjoint<TAPS>(jf, jl, m) && !__any(wr && (rp > m - TAPS || rm > m - TAPS))) {
-        spread_pair_wave<TAPS>(G, rp, rm, wr, vp, vm, w, wm, sg);
+        spread_pair_wave<T, TAPS>(G, rp, rm, wr, vp, vm, w, wm, sg);
       } else {
-        spread_pass_wave<TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
+        spread_pass_wave<T, TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
         if (anyon) {
-          spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
+          spread_pass_wave<T, TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
         } else {
-          spread_pass_wave<TAPS, P2>(G, m, jm, act, nact, vm, wm, sg);
+          spread_pass_wave<T, TAPS, P2>(G, m, jm, act, nact, vm, wm, sg);
         }
       }
     }
@@ -3434,16 +3448,16 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft1_c(StageArgs a) {
   PAT_END_ITEM
 }
 
-// The fused type-1 kernel with wavefront spreading (FP32, m = 2^LM and
-// nz = 2^LZ at compile time): a work item holds one line per wavefront.  The
+// The fused type-1 kernel with wavefront spreading (FP32 at four waves per
+// SIMD, FP64 at two; m = 2^LM and nz = 2^LZ at compile time): a work item
+// holds one line per wavefront.  The
 // depth DFTs of its lines run together, then each wavefront spreads its line
 // into its own grid line in LDS (no block barrier inside), and the grid DFTs
 // of all lines run together; the last stage writes the picked, deconvolved
 // samples to memory.  LDS: the lines' grids (also the depth-FFT scratch) and
 // their depth spectra in natural order.
-template <int TAPS, int LM, int LZ>
-__global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
-  using T = float;
+template <typename T, int TAPS, int LM, int LZ>
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft1_w(StageArgs a) {
   constexpr int m = 1 << LM, nz = 1 << LZ, NL = kBlock / 64;
   using PM = P2Plan<LM, p2_l16_m(LM)>;  // (radix-16 last stages, as in the type-2 kernel)
   using PZ = P2Plan<LZ, p2_l16_z(LZ)>;
@@ -3473,7 +3487,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_line_nufft1_w(StageArgs a) {
   const int wv = (int)(threadIdx.x >> 6);
   if (wv < nl) {
     const cx<T>* qb = qn + wv * nz;
-    spread_line_wave<TAPS, true>(I, a, line0 + wv, a.mode, m, nz, grid + wv * m, [&](int l) { return qb[l]; });
+    spread_line_wave<T, TAPS, true>(I, a, line0 + wv, a.mode, m, nz, grid + wv * m, [&](int l) { return qb[l]; });
   }
   __syncthreads();
   // X_n = s_n conj(G_k) for the natural index k = (n - nt/2) mod m
@@ -3508,7 +3522,7 @@ __global__ __launch_bounds__(kBlock) void k_line_spread_w(StageArgs a) {
     const int line = line0 + wv;
     cx<float>* Gl = reinterpret_cast<cx<float>*>(pat_smem) + wv * m;
     const cx<float>* F = static_cast<const cx<float>*>(a.in[inst_]) + (size_t)line * nz;
-    spread_line_wave<TAPS, P2>(I, a, line, a.mode, m, nz, Gl, [&](int l) { return F[l]; });
+    spread_line_wave<float, TAPS, P2>(I, a, line, a.mode, m, nz, Gl, [&](int l) { return F[l]; });
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     G* row = static_cast<G*>(a.out[inst_]) + (size_t)line * m;
     for (int j = 4 * L; j < m; j += 4 * 64) {
@@ -3882,23 +3896,23 @@ struct Runner {
                   max_over([](const Inst& I) { return lds_fused2(I, cs); }), st, tm);
   }
   hipError_t nufft1(const void* const* in, void* const* out, int mode) {
-    if constexpr (sizeof(T) == 4 && P2 && TAPS > 0 && TAPS % 2 == 0) {
+    if constexpr (P2 && TAPS > 0 && TAPS % 2 == 0) {
       // one line per wavefront, compile-time sizes for m = 2^8 .. 2^10 and
       // nz = m/4 or m/2
       const Inst& I = h[0];
       const int lm = __builtin_ctz((unsigned)I.m), dz = lm - __builtin_ctz((unsigned)I.nz);
       StageArgs a = base(IT_LWAVE, true, mode, in, out);
       if (n == 1 && a.pair_ok && (dz == 1 || dz == 2) && lm >= 8 && lm <= 10) {
-        const size_t shm = lds_fused1_wave(I);
+        const size_t shm = lds_fused1_wave(I, cs);
         auto go = [&](auto kern) { return launch(kern, "nufft_adjoint_fused", a, shm, st, tm); };
         if (dz == 2) {
-          if (lm == 8) return go(k_line_nufft1_w<TAPS, 8, 6>);
-          if (lm == 9) return go(k_line_nufft1_w<TAPS, 9, 7>);
-          return go(k_line_nufft1_w<TAPS, 10, 8>);
+          if (lm == 8) return go(k_line_nufft1_w<T, TAPS, 8, 6>);
+          if (lm == 9) return go(k_line_nufft1_w<T, TAPS, 9, 7>);
+          return go(k_line_nufft1_w<T, TAPS, 10, 8>);
         }
-        if (lm == 8) return go(k_line_nufft1_w<TAPS, 8, 7>);
-        if (lm == 9) return go(k_line_nufft1_w<TAPS, 9, 8>);
-        return go(k_line_nufft1_w<TAPS, 10, 9>);
+        if (lm == 8) return go(k_line_nufft1_w<T, TAPS, 8, 7>);
+        if (lm == 9) return go(k_line_nufft1_w<T, TAPS, 9, 8>);
+        return go(k_line_nufft1_w<T, TAPS, 10, 9>);
       }
       next_counter--;
     }

@@ -120,7 +120,9 @@ inline size_t lds_fused2(const Inst& I, size_t cs) {
 // wavefront of the workgroup (stand-alone), plus the depth spectra in the
 // fused type-1 kernel
 inline size_t lds_spread_wave(const Inst& I) { return (size_t)(kBlock / 64) * I.m * 8; }
-inline size_t lds_fused1_wave(const Inst& I) { return (size_t)(kBlock / 64) * ((size_t)I.m + I.nz) * 8; }
+inline size_t lds_fused1_wave(const Inst& I, size_t cs) {
+  return (size_t)(kBlock / 64) * ((size_t)I.m + I.nz) * cs;
+}
 // fused type-1 line kernel: a region of max(m, lpw_a nz) (the depth FFTs,
 // then one grid line), lpw_a depth spectra in natural order, the lists
 inline size_t lds_fused1(const Inst& I, size_t cs) {

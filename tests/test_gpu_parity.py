@@ -195,9 +195,10 @@ def test_pipelined_kernels_match_one_tile_kernels(g):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_spreading_repeats_bit_for_bit(prec):
-    """Spreading gathers each cell's nodes in node order, with no atomics:
-    repeated runs of R^T and A agree bit for bit (128^3 volume, whose lines
-    of large |K| crowd many nodes into a few cells)."""
+    """Spreading sums each cell's terms in a fixed order (segmented scans
+    across a wavefront's lanes, or the gather over a cell's nodes), with no
+    atomics: repeated runs of R^T and A agree bit for bit (128^3 volume,
+    whose lines of large |K| crowd many nodes into a few cells)."""
     g = geo(128, 128, 256, 128, 1 / 128, 1 / 128, 1 / 128)
     say(f"repeatability {prec} {g}")
     plan = make_plan(g, prec)
