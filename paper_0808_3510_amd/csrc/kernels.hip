@@ -3087,16 +3087,6 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft2_
   }
 }
 
-// k_line_nufft2_pipe_c for R on 3D plans whose depth lines are a quarter of
-// the grid lines (nz = m/4, m = 2^LM), with NT threads: a work item holds
-// NL = 16 NT/m lines, taken in mirror pairs (mirror_line), in 16 NT padded
-// points of LDS (four waves per SIMD).  Each thread runs two first-stage
-// butterflies, and in the interpolation one node pair of one mirror pair:
-// its window, phase and weight serve both lines (the two lines of a pair
-// with r = 0 form their own).  The last grid-FFT stage works in place: every
-// thread reads its butterflies' 16 points, and after a barrier writes them
-// in natural order over the scratch; the interpolation outputs wait in
-// registers for a barrier and then overwrite the grid as the depth lines.
 // Entries k < L / r of the twiddle table that the twiddled stages (all but
 // the last) of a compile-time plan read, r the smallest of their radices.
 template <typename Pl, int L>
@@ -3130,6 +3120,17 @@ static_assert(MirrorLds<float, 10, 256>::TWM == 128 && MirrorLds<float, 10, 256>
                   MirrorLds<double, 10, 128>::fits && MirrorLds<double, 11, 256>::fits,
               "the resident waves per SIMD fit in LDS");
 
+// k_line_nufft2_pipe_c for R on 3D plans whose depth lines are a quarter of
+// the grid lines (nz = m/4, m = 2^LM), with NT threads: a work item holds
+// NL = 16 NT/m lines, taken in mirror pairs (mirror_line), in 16 NT padded
+// points of LDS (four waves per SIMD in FP32, two in FP64).  Each thread runs
+// two first-stage butterflies, and in the interpolation one node pair of one
+// mirror pair: its window, phase and weight serve both lines (the two lines
+// of a pair with r = 0 form their own).  The last grid-FFT stage works in
+// place: every thread reads its butterflies' 16 points, and after a barrier
+// writes them in natural order over the scratch; the interpolation outputs
+// wait in registers for a barrier and then overwrite the grid as the depth
+// lines.
 template <typename T, int TAPS, int LM, int LZ, int NT>
 __global__ __launch_bounds__(NT, mirror_waves<T>()) void k_line_nufft2_mirror(StageArgs a) {
   const Inst& I = *a.inst[0];
@@ -3450,12 +3451,12 @@ __global__ __launch_bounds__(kBlock, 5) void k_line_nufft1_c(StageArgs a) {
 
 // The fused type-1 kernel with wavefront spreading (FP32 at four waves per
 // SIMD, FP64 at two; m = 2^LM and nz = 2^LZ at compile time): a work item
-// holds one line per wavefront.  The
-// depth DFTs of its lines run together, then each wavefront spreads its line
-// into its own grid line in LDS (no block barrier inside), and the grid DFTs
-// of all lines run together; the last stage writes the picked, deconvolved
-// samples to memory.  LDS: the lines' grids (also the depth-FFT scratch) and
-// their depth spectra in natural order.
+// holds one line per wavefront.  The depth DFTs of its lines run together,
+// then each wavefront spreads its line into its own grid line in LDS (no
+// block barrier inside), and the grid DFTs of all lines run together; the
+// last stage writes the picked, deconvolved samples to memory.  LDS: the
+// lines' grids (also the depth-FFT scratch) and their depth spectra in
+// natural order.
 template <typename T, int TAPS, int LM, int LZ>
 __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? 4 : 2) void k_line_nufft1_w(StageArgs a) {
   constexpr int m = 1 << LM, nz = 1 << LZ, NL = kBlock / 64;
