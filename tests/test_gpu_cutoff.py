@@ -18,6 +18,9 @@ CASES = [
     (dict(n1=24, n2=1, nt=48, nz=24, dx=1.0, dt=0.8, dz=1.2, vs=1.0), 2.5),
     # 3D, factors 3, 5, 7, rows of 70 samples (two-sample accesses), 4 eps = n1
     (dict(n1=12, n2=20, nt=70, nz=18, dx=1.0, dt=0.8, dz=1.2, vs=1.0), 3.0),
+    # 3D, 128-point x1 columns: the passes over x1 take their compile-time
+    # pipelines (FP32 and FP64), the weighted one included; 4 eps = n2
+    (dict(n1=128, n2=4, nt=32, nz=16, dx=1 / 128, dt=1 / 32, dz=1 / 16, vs=1.0), 1.0),
 ]
 
 
