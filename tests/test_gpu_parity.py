@@ -271,3 +271,25 @@ def test_long_grid_lines_match_oracle(op, prec, c, K):
     y = getattr(plan, op)(to_dev(x, prec))
     torch.cuda.synchronize()
     assert relerr(y.cpu().double().numpy(), expect) < TOL[prec]
+
+
+@pytest.mark.parametrize("op", ["reconstruct", "reconstruct_adjoint"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("g", [
+    geo(128, 4, 16, 8, 1.0, 0.9, 1.1),   # x1 columns of 128, 256 and 512 points:
+    geo(256, 4, 16, 8, 1.0, 0.9, 1.1),   # the compile-time x1 and c2r pipelines
+    geo(512, 4, 16, 8, 1.0, 0.9, 1.1),
+    geo(4, 128, 16, 8, 1.0, 0.9, 1.1),   # x2 columns of 128, 256 and 512 points
+    geo(4, 256, 16, 8, 1.0, 0.9, 1.1),
+    geo(4, 512, 16, 8, 1.0, 0.9, 1.1),
+])
+def test_transverse_pipelines_every_length(g, prec, op):
+    """The transverse passes' compile-time pipelines (tile widths 16 / 8 in
+    FP32, 8 / 4 in FP64) against the oracle at every length they cover."""
+    say(f"transverse pipelines {op} {prec} {g}")
+    n_in = g["nz"] if op == "reconstruct_adjoint" else g["nt"]
+    x = inputs.random_array((g["n1"], g["n2"], n_in), 760)
+    plan = make_plan(g, prec)
+    y = getattr(plan, op)(to_dev(x, prec))
+    torch.cuda.synchronize()
+    assert relerr(y.cpu().double().numpy(), getattr(recon, op)(x, g)) < TOL[prec]
