@@ -1037,7 +1037,8 @@ template <typename T, int TAPS>
 struct PairWin {
   cx<T> ph;    // exp(-i pi nup) (1 on an uncentred grid)
   int jp, jn;  // first taps of +nup and -nup, in [0, m)
-  T w[TAPS], wm[TAPS];
+  bool on;     // node on a grid point: -nup takes w itself, not reversed
+  T w[TAPS];
 };
 template <typename T, int TAPS, bool P2>
 __device__ __forceinline__ void pair_window(double nup, const Inst& I, const StageArgs& a, int m, double inv_m,
@@ -1049,8 +1050,7 @@ __device__ __forceinline__ void pair_window(double nup, const Inst& I, const Sta
   const T x = (T)(2.0 * d + 1.0);
   const bool ongrid = d == -1.0;
   tap_weights_pairs<T, TAPS>(a, x, pw.w);
-#pragma unroll
-  for (int t = 0; t < TAPS; ++t) pw.wm[t] = bitsel(ongrid, pw.w[t], pw.w[TAPS - 1 - t]);
+  pw.on = ongrid;
   const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
   pw.jp = wrap_tap<P2>(j0, m, inv_m);
   pw.jn = wrap_tap<P2>(jm, m, inv_m);
@@ -1061,22 +1061,34 @@ template <typename T, int TAPS, bool HALO>
 __device__ __forceinline__ void pair_values(const cx<T>* U, int m, const PairWin<T, TAPS>& pw, cx<T>* vp,
                                             cx<T>* vn) {
   cx<T> sp, sn;
+  // the weights of -nup: w reversed, or w itself on a grid point (the
+  // reversal costs nothing where no lane of the wave is on one)
+  const bool anyon = __any(pw.on);
+  auto wm = [&](int t) { return bitsel(pw.on, pw.w[t], pw.w[TAPS - 1 - t]); };
   if (HALO || (pw.jp <= m - TAPS && pw.jn <= m - TAPS)) {
     // both windows in one loop: two independent sums, two reads in flight
     const cx<T>* up = U + pw.jp;
     const cx<T>* un = U + pw.jn;
     sp = sn = mk(T(0), T(0));
+    auto sums = [&](auto wmt) {
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
-      const cx<T> g = up[t], h = un[t];
-      sp.x += pw.w[t] * g.x;
-      sp.y += pw.w[t] * g.y;
-      sn.x += pw.wm[t] * h.x;
-      sn.y += pw.wm[t] * h.y;
-    }
+      for (int t = 0; t < TAPS; ++t) {
+        const cx<T> g = up[t], h = un[t];
+        const T b = wmt(t);
+        sp.x += pw.w[t] * g.x;
+        sp.y += pw.w[t] * g.y;
+        sn.x += b * h.x;
+        sn.y += b * h.y;
+      }
+    };
+    if (anyon) sums(wm);
+    else sums([&](int t) { return pw.w[TAPS - 1 - t]; });
   } else {
+    T wms[TAPS];
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) wms[t] = wm(t);
     sp = taps_at<T, TAPS, HALO>(U, m, pw.jp, pw.w);
-    sn = taps_at<T, TAPS, HALO>(U, m, pw.jn, pw.wm);
+    sn = taps_at<T, TAPS, HALO>(U, m, pw.jn, wms);
   }
   *vp = cmul(sp, pw.ph);
   *vn = cmul(sn, cconj(pw.ph));
