@@ -1549,19 +1549,21 @@ __device__ __forceinline__ void spread_pass_wave(cx<T>* G, int m, int j0, bool a
 }
 
 // Both passes of a batch at once, for the common case that spread_line_wave
-// checks: no node on a grid point (so the passes share their segments),
+// checks: no node on a grid point (so the passes share their segments, and
+// the weights of -nu+ are those of +nu+ reversed),
 // neither pass's writers wrap past the end of the line, and the cells of the
 // two passes are disjoint.  Each cell then receives the same terms in the
 // same order as in two separate passes, and a round's two read-add-write
 // chains overlap.  rp, rm: first taps mod m.
 template <typename T, int TAPS>
 __device__ __forceinline__ void spread_pair_wave(cx<T>* G, int rp, int rm, bool wr, cx<T> vp, cx<T> vm, const T* w,
-                                                 const T* wm, const WaveSeg& sg) {
+                                                 const WaveSeg& sg) {
   cx<T>* gp = G + rp;
   cx<T>* gm = G + rm;
 #pragma unroll
   for (int t = 0; t < TAPS; ++t) {
-    T xp = w[t] * vp.x, yp = w[t] * vp.y, xm = wm[t] * vm.x, ym = wm[t] * vm.y;
+    const T b = w[TAPS - 1 - t];  // -nu+: w reversed (no node on a grid point)
+    T xp = w[t] * vp.x, yp = w[t] * vp.y, xm = b * vm.x, ym = b * vm.y;
     seg_sum2(sg, xp, yp, xm, ym);
     if (wr) {
       const cx<T> a = gp[t], b = gm[t];
@@ -1678,12 +1680,18 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
     const double d = tap_origin(I.c * nup, I.ck, &j0);
     const T x = (T)(2.0 * d + 1.0);
     const bool ongrid = d == -1.0;
-    T w[TAPS], wm[TAPS];
+    T w[TAPS];
     tap_weights_pairs<T, TAPS>(a, x, w);
+    // the weights of -nu+ (w reversed, or w on a grid point), formed only on
+    // the paths that hold them
+    auto mirror_weights = [&](T* wm) {
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
+      for (int t = 0; t < TAPS; ++t) wm[t] = bitsel(ongrid, w[t], w[TAPS - 1 - t]);
+    };
     const int jm = ongrid ? -(j0 + TAPS - 2) : -(j0 + TAPS - 1);
     if (2 * nact * TAPS <= 64) {
+      T wm[TAPS];
+      mirror_weights(wm);
       // nodes +nu+ of lanes 0 .. nact-1, then -nu+ of the same lanes
       const int n2 = 2 * nact;
       const int src = L < nact ? L : L - nact;
@@ -1725,8 +1733,11 @@ __device__ __forceinline__ void spread_line_wave(const Inst& I, const StageArgs&
       }
       const bool wr = act && sg.tail;
       if (!anyon && passes_disjoint<TAPS>(jf, jl, m) && !__any(wr && (rp > m - TAPS || rm > m - TAPS))) {
-        spread_pair_wave<T, TAPS>(G, rp, rm, wr, vp, vm, w, wm, sg);
+        // (no node on a grid point: -nu+ takes w reversed)
+        spread_pair_wave<T, TAPS>(G, rp, rm, wr, vp, vm, w, sg);
       } else {
+        T wm[TAPS];
+        mirror_weights(wm);
         spread_pass_wave<T, TAPS, P2>(G, m, j0, act, nact, vp, w, sg);
         if (anyon) {
           spread_pass_wave<T, TAPS, P2>(G, m, jm, act, nact, vm, wm, pass_segments(jm, act));
